@@ -1,0 +1,163 @@
+#!/usr/bin/env python3
+"""Benchmark of the PDE signature-kernel Gram batch on one MI355X.
+
+Workload (a "step"): the full 128 x 128 Gram matrix of two batches of 256-point
+paths in R^8 with a time channel appended (d = 9), Gaussian increments with std
+0.3/sqrt(256), dyadic order 1: increments, increment Gram and the explicit
+sweep over 16384 pairs x 510 x 510 fine cells = 4.26e9 cell updates.  Inputs
+are resident in HBM before the timed region; every step recomputes everything.
+
+Prints ONE JSON line:
+  value       grid-cell updates per second (whole job, one GPU)
+  roofline    the sweep kernel against the VALU issue rate
+  cpu_baseline the FP64 oracle on the host cores, on a bounded sample
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Goursat grid-cell updates/s (Gram batch) and pairs/s at stated rel err vs FP64"
+
+# MI355X FP64 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz double operations
+# per second (78.6 TFLOP/s counting an FMA as two); non-packed float32
+# add/FMA issue at twice this rate.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-pairs", type=int, default=0,
+                    help="pairs of the workload timed on the CPU oracle (0: auto)")
+    return ap.parse_args()
+
+
+def sweep_ops_per_cell(d: int, lam: int) -> float:
+    """VALU work per fine cell in FP64-operation equivalents: the cell update
+    (one double add and one double FMA) plus the coarse inner product (d float
+    FMAs per coarse cell, shared by 4^lam fine cells; a float FMA issues at
+    twice the double rate, so it counts 1/2)."""
+    return 2.0 + 0.5 * d / float(4 ** lam)
+
+
+def cpu_baseline(X, Y, lam, n_sample, K_gpu):
+    """Time the FP64 oracle on a seeded sample of the workload's pairs, on all
+    host threads, and report the GPU output's error on the same pairs."""
+    import oracle
+    rng = np.random.default_rng(1)
+    nx, ny = X.shape[0], Y.shape[0]
+    idx = rng.choice(nx * ny, size=n_sample, replace=False)
+    xs = [X[i // ny].astype(np.float64) for i in idx]
+    ys = [Y[i % ny].astype(np.float64) for i in idx]
+    threads = oracle.max_threads()
+    oracle.pairs(xs[:8], ys[:8], lam)  # load + warm
+    t0 = time.perf_counter()
+    ref = oracle.pairs(xs, ys, lam, nthreads=threads)
+    dt = time.perf_counter() - t0
+    cells = n_sample * ((X.shape[1] - 1) << lam) * ((Y.shape[1] - 1) << lam)
+    err = np.abs(K_gpu.reshape(-1)[idx] - ref) / np.maximum(1.0, np.abs(ref))
+    return {"value": cells / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_sample} of the {nx * ny} Gram pairs (seeded), all host threads, "
+                      f"{dt:.2f} s",
+            "gpu_max_err_on_sample": float(err.max())}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2006_14794_amd as sk
+    import workloads
+
+    lam = 1
+    X, Y = workloads.gram_batch()
+    nx, L, d = X.shape
+    ny = Y.shape[0]
+    dev = torch.device("cuda:0")
+    Xt = torch.from_numpy(X).to(dev)
+    Yt = torch.from_numpy(Y).to(dev)
+    out = torch.empty((nx, ny), dtype=torch.float32, device=dev)
+    ws = torch.empty(sk.workspace_bytes(1, Xt, Yt, lam, 0), dtype=torch.uint8, device=dev)
+
+    def step():
+        sk.sigkernel_gram(Xt, Yt, lam, out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        step()
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    ms_per_step = wall * 1e3 / args.steps
+
+    M, N = (L - 1) << lam, (L - 1) << lam
+    cells = nx * ny * M * N
+    value = cells / (ms_per_step / 1e3)
+    pairs_per_s = nx * ny / (ms_per_step / 1e3)
+
+    avg_launch_s = float(np.mean(per_launch_ms)) / 1e3
+    ops = cells * sweep_ops_per_cell(d, lam)
+    achieved = ops / avg_launch_s / 1e12
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "gram 128x128 pairs, 256-point paths, d=8+time, dyadic order 1",
+                   "pairs": nx * ny, "fine_cells_per_pair": M * N, "sweep_state": "f64",
+                   "increment_gram": "f32"},
+        "pairs_per_s": pairs_per_s,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": VALU_PEAK_TOPS,
+            "unit": "Tops/s",
+            "frac": achieved / VALU_PEAK_TOPS,
+            "traffic": None,
+            "kernel": "sweep_kernel (per-call events: increments + sweep)",
+            "avg_launch_ms": avg_launch_s * 1e3,
+            "ops_per_cell": sweep_ops_per_cell(d, lam),
+        },
+    }
+    if not args.no_cpu_baseline:
+        n_sample = args.cpu_sample_pairs or 4096
+        rec["cpu_baseline"] = cpu_baseline(X, Y, lam, n_sample, out.cpu().numpy())
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

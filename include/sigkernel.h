@@ -1,0 +1,120 @@
+/*
+ * sigkernel.h -- C ABI of the MI355X (gfx950) PDE signature kernel library.
+ *
+ * Paper: Salvi, Cass, Foster, Lyons, Yang, "The Signature Kernel is the
+ * solution of a Goursat PDE", arXiv 2006.14794.
+ *
+ * The library evaluates, for pairs of piecewise-linear paths x (lx points) and
+ * y (ly points) in R^d, the explicit finite-difference scheme of Section 3.1,
+ * eq. (explicit_finite_diff), on the dyadic grid P_lambda of definition
+ * (fintite_diff): the coarse increment inner products <x_{p+1}-x_p,
+ * y_{q+1}-y_q> (Section 3.1, piecewise-linear case), refined by the factor
+ * 2^{-2 lambda} (remark after eq. (explicit_finite_diff)), and swept from the
+ * boundary values 1 (eq. (PDE), Theorem thm:PDE) to the terminal corner.
+ * Rows of the fine grid follow x, columns follow y; the fine grid has
+ * (2^lambda (lx-1) + 1) x (2^lambda (ly-1) + 1) nodes.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All point and output buffers are DEVICE memory owned by the caller.  The
+ *    library allocates no device memory: scratch space comes from the caller's
+ *    workspace (size from sigkernel_workspace_bytes).  Nothing is retained
+ *    after a call returns.
+ *  - Calls enqueue work on `stream` (a hipStream_t, NULL = default stream) and
+ *    return immediately.  The status reports argument validation and launch
+ *    only; kernel faults surface at the next synchronisation.
+ *  - On any error nothing is enqueued and outputs are left untouched.
+ *  - NaN/Inf inputs are not scanned: they propagate into the outputs of the
+ *    pairs that contain them and into no other pair.
+ *  - A path with one point has no increments: its kernel with any path is 1
+ *    (the boundary value) and its gradient is 0.
+ *  - Entry points are reentrant; calls that write the same output or
+ *    workspace concurrently race.
+ */
+#ifndef SIGKERNEL_H
+#define SIGKERNEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sk_status;
+enum {
+    SK_OK = 0,
+    SK_ERR_NULL = -1,        /* a required pointer is NULL                         */
+    SK_ERR_SHAPE = -2,       /* d < 1, a length < 1, dims or counts inconsistent   */
+    SK_ERR_ORDER = -3,       /* dyadic order < 0 or beyond what is supported        */
+    SK_ERR_WORKSPACE = -4,   /* workspace NULL or smaller than required             */
+    SK_ERR_FLAGS = -5,       /* unknown or incompatible flag bits                   */
+    SK_ERR_HIP = -6,         /* a HIP launch failed                                 */
+    SK_ERR_UNSUPPORTED = -7  /* shape outside the compiled kernel configurations    */
+};
+
+/*
+ * A batch of paths in R^dim, float32, row-major.
+ *  - Uniform batch (offsets == NULL): points is [n_paths][len][dim].
+ *  - Ragged batch (offsets != NULL): offsets is a DEVICE array of n_paths+1
+ *    int64, offsets[0] == 0, non-decreasing; path k is points
+ *    [offsets[k], offsets[k+1]) of points [offsets[n_paths]][dim].  `len`
+ *    must then be an upper bound of every path length; a pair whose path
+ *    breaks that bound or has length < 1 gets a NaN output.
+ */
+typedef struct sk_paths {
+    const float *points;
+    const int64_t *offsets;
+    int64_t n_paths;
+    int32_t len;
+    int32_t dim;
+} sk_paths;
+
+/*
+ * Precision: path points and outputs are float32; the increments and their
+ * inner products are formed in float32 (FMA), and the sweep state -- every
+ * node value of the scheme -- is IEEE double.
+ */
+
+/* flags */
+enum {
+    SK_SYMMETRIC = 1u << 0,   /* gram only: X and Y are the same batch; solve a <= b and mirror */
+    SK_NO_DIAG   = 1u << 1    /* gram only, with SK_SYMMETRIC: write 0 on the diagonal         */
+};
+
+/*
+ * sigkernel_pair -- independent pairs (Section 3.1, eq. (explicit_finite_diff)).
+ *   out[k] = k_hat(x_k, y_k) at the terminal corner of P_lambda, k < n_paths.
+ * x->n_paths must equal y->n_paths and x->dim == y->dim.
+ * out: DEVICE float[n_paths].  ws: DEVICE workspace of at least
+ * sigkernel_workspace_bytes(SK_OP_PAIR, ...) bytes.
+ */
+sk_status sigkernel_pair(const sk_paths *x, const sk_paths *y, int32_t dyadic_order,
+                         uint32_t flags, float *out, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/*
+ * sigkernel_gram -- Gram matrix of two batches (Section 3.1 scheme applied to
+ * every pair; the Gram matrices are what the applications of Section 5 consume).
+ *   K[a * Y->n_paths + b] = k_hat(X_a, Y_b).
+ * K: DEVICE float[X->n_paths * Y->n_paths], row-major.
+ */
+sk_status sigkernel_gram(const sk_paths *X, const sk_paths *Y, int32_t dyadic_order,
+                         uint32_t flags, float *K, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* Workspace sizing.  op is one of the SK_OP_* values. */
+enum { SK_OP_PAIR = 0, SK_OP_GRAM = 1, SK_OP_GRAM_BACKWARD = 2 };
+size_t sigkernel_workspace_bytes(int32_t op, const sk_paths *X, const sk_paths *Y,
+                                 int32_t dyadic_order, uint32_t flags);
+
+/* Human-readable name of a status code (static storage). */
+const char *sigkernel_status_string(sk_status status);
+
+/* Library version, "major.minor.patch" (static storage). */
+const char *sigkernel_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIGKERNEL_H */

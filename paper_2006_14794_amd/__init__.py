@@ -1,0 +1,17 @@
+"""MI355X-native (gfx950) PDE signature kernel.
+
+Hot path of Salvi et al., "The Signature Kernel is the solution of a Goursat
+PDE" (arXiv 2006.14794), Section 3.1: increment inner products of two
+piecewise-linear paths, their dyadic refinement, and the explicit
+finite-difference sweep of the Goursat problem to the terminal corner -- as
+hand-written HIP kernels behind a C ABI (include/sigkernel.h).  This package
+is the thin Python binding; it never computes anything on the CPU.
+"""
+from ._lib import SK_NO_DIAG, SK_SYMMETRIC, SigKernelError, load, status_string, version
+from .api import RaggedPaths, sigkernel_gram, sigkernel_pair, workspace_bytes
+
+__all__ = [
+    "RaggedPaths", "SigKernelError", "load", "sigkernel_gram", "sigkernel_pair",
+    "status_string", "version", "workspace_bytes",
+    "SK_SYMMETRIC", "SK_NO_DIAG",
+]

@@ -1,0 +1,98 @@
+"""ctypes binding of libsigkernel.so (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``csrc/``; this module only turns
+torch tensors into the plain pointers and sizes of ``include/sigkernel.h``.
+If the library has not been built the first call raises immediately: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsigkernel.so")
+
+SK_OK = 0
+SK_ERR_NULL = -1
+SK_ERR_SHAPE = -2
+SK_ERR_ORDER = -3
+SK_ERR_WORKSPACE = -4
+SK_ERR_FLAGS = -5
+SK_ERR_HIP = -6
+SK_ERR_UNSUPPORTED = -7
+
+SK_SYMMETRIC = 1 << 0
+SK_NO_DIAG = 1 << 1
+
+SK_OP_PAIR = 0
+SK_OP_GRAM = 1
+SK_OP_GRAM_BACKWARD = 2
+
+# Every symbol the header declares (checked by the CPU test suite).
+EXPORTED = (
+    "sigkernel_pair",
+    "sigkernel_gram",
+    "sigkernel_workspace_bytes",
+    "sigkernel_status_string",
+    "sigkernel_version",
+)
+
+
+class SkPaths(ctypes.Structure):
+    _fields_ = [
+        ("points", ctypes.c_void_p),
+        ("offsets", ctypes.c_void_p),
+        ("n_paths", ctypes.c_int64),
+        ("len", ctypes.c_int32),
+        ("dim", ctypes.c_int32),
+    ]
+
+
+class SigKernelError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} (status {status})")
+
+
+_lib = None
+
+
+def load():
+    """Load libsigkernel.so; raise if it is missing (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"libsigkernel.so not found at {LIB_PATH}: build it with "
+            "`python -c 'import __graft_entry__ as g; g.build()'` "
+            "(hipcc, gfx950). There is no CPU fallback.")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(SkPaths)
+    vp, i32, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
+    lib.sigkernel_pair.argtypes = [P, P, i32, u32, vp, vp, sz, vp]
+    lib.sigkernel_pair.restype = i32
+    lib.sigkernel_gram.argtypes = [P, P, i32, u32, vp, vp, sz, vp]
+    lib.sigkernel_gram.restype = i32
+    lib.sigkernel_workspace_bytes.argtypes = [i32, P, P, i32, u32]
+    lib.sigkernel_workspace_bytes.restype = sz
+    lib.sigkernel_status_string.argtypes = [i32]
+    lib.sigkernel_status_string.restype = ctypes.c_char_p
+    lib.sigkernel_version.argtypes = []
+    lib.sigkernel_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load().sigkernel_status_string(int(status)).decode()
+
+
+def version() -> str:
+    return load().sigkernel_version().decode()
+
+
+def check(status: int, what: str) -> None:
+    if status != SK_OK:
+        raise SigKernelError(status, what)

@@ -1,0 +1,151 @@
+"""Torch-facing wrappers of the C ABI (same names as the C entry points).
+
+PyTorch supplies device memory and the current HIP stream; every step of the
+computation runs in libsigkernel's HIP kernels.  Inputs are float32 CUDA (HIP)
+tensors:
+
+* a uniform batch is a contiguous ``[n_paths, len, dim]`` tensor;
+* a ragged batch is a :class:`RaggedPaths` (``points [total, dim]``, device
+  ``offsets [n_paths + 1]`` int64, and an upper bound ``max_len``).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Union
+
+import torch
+
+from . import _lib
+from ._lib import SkPaths
+
+
+@dataclass
+class RaggedPaths:
+    points: torch.Tensor   # [total, dim] float32, device
+    offsets: torch.Tensor  # [n_paths + 1] int64, device
+    max_len: int
+
+    @staticmethod
+    def from_list(paths, device) -> "RaggedPaths":
+        lens = [int(p.shape[0]) for p in paths]
+        off = [0]
+        for L in lens:
+            off.append(off[-1] + L)
+        pts = torch.cat([torch.as_tensor(p, dtype=torch.float32) for p in paths], 0)
+        return RaggedPaths(pts.to(device).contiguous(),
+                           torch.tensor(off, dtype=torch.int64, device=device),
+                           max(lens) if lens else 1)
+
+    @property
+    def n_paths(self) -> int:
+        return int(self.offsets.numel()) - 1
+
+    @property
+    def dim(self) -> int:
+        return int(self.points.shape[1])
+
+
+PathsLike = Union[torch.Tensor, RaggedPaths]
+
+
+def _describe(p: PathsLike) -> SkPaths:
+    if isinstance(p, RaggedPaths):
+        if p.points.dtype != torch.float32 or not p.points.is_cuda:
+            raise TypeError("ragged points must be a float32 device tensor")
+        if p.offsets.dtype != torch.int64 or not p.offsets.is_cuda:
+            raise TypeError("offsets must be an int64 device tensor")
+        if not p.points.is_contiguous() or not p.offsets.is_contiguous():
+            raise ValueError("ragged tensors must be contiguous")
+        return SkPaths(p.points.data_ptr(), p.offsets.data_ptr(), p.n_paths,
+                       int(p.max_len), p.dim)
+    if not isinstance(p, torch.Tensor) or p.dim() != 3:
+        raise TypeError("expected a [n_paths, len, dim] tensor or RaggedPaths")
+    if p.dtype != torch.float32 or not p.is_cuda:
+        raise TypeError("paths must be a float32 device tensor")
+    if not p.is_contiguous():
+        raise ValueError("paths must be contiguous")
+    return SkPaths(p.data_ptr() if p.numel() else 0, None, int(p.shape[0]),
+                   int(p.shape[1]), int(p.shape[2]))
+
+
+def _device(p: PathsLike) -> torch.device:
+    return p.points.device if isinstance(p, RaggedPaths) else p.device
+
+
+def _n_paths(p: PathsLike) -> int:
+    return p.n_paths if isinstance(p, RaggedPaths) else int(p.shape[0])
+
+
+def _stream_ptr(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def workspace_bytes(op: int, X: PathsLike, Y: PathsLike, dyadic_order: int,
+                    flags: int = 0) -> int:
+    lib = _lib.load()
+    sx, sy = _describe(X), _describe(Y)
+    return int(lib.sigkernel_workspace_bytes(op, ctypes.byref(sx), ctypes.byref(sy),
+                                             int(dyadic_order), int(flags)))
+
+
+def _workspace(nbytes: int, device, ws: Optional[torch.Tensor]) -> torch.Tensor:
+    if ws is not None:
+        if ws.numel() * ws.element_size() < nbytes:
+            raise ValueError("workspace too small")
+        return ws
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def sigkernel_pair(x: PathsLike, y: PathsLike, dyadic_order: int = 0, *,
+                   out: Optional[torch.Tensor] = None,
+                   workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """out[k] = k_hat(x_k, y_k) of the explicit scheme on P_lambda."""
+    lib = _lib.load()
+    dev = _device(x)
+    n = _n_paths(x)
+    flags = 0
+    sx, sy = _describe(x), _describe(y)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=dev)
+    nbytes = int(lib.sigkernel_workspace_bytes(_lib.SK_OP_PAIR, ctypes.byref(sx),
+                                               ctypes.byref(sy), dyadic_order, flags))
+    ws = _workspace(nbytes, dev, workspace)
+    st = lib.sigkernel_pair(ctypes.byref(sx), ctypes.byref(sy), int(dyadic_order), flags,
+                            out.data_ptr() if n else None, ws.data_ptr(),
+                            ws.numel() * ws.element_size(), _stream_ptr(dev))
+    _lib.check(st, "sigkernel_pair")
+    return out
+
+
+def sigkernel_gram(X: PathsLike, Y: Optional[PathsLike] = None, dyadic_order: int = 0, *,
+                   symmetric: bool = False, no_diag: bool = False,
+                   out: Optional[torch.Tensor] = None,
+                   workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """K[a, b] = k_hat(X_a, Y_b).  ``symmetric=True`` (Y omitted or X itself)
+    solves a <= b only and mirrors; ``no_diag`` then writes 0 on the diagonal."""
+    lib = _lib.load()
+    if Y is None:
+        Y = X
+    if symmetric and Y is not X:
+        raise ValueError("symmetric Gram needs Y to be X")
+    dev = _device(X)
+    nx, ny = _n_paths(X), _n_paths(Y)
+    flags = 0
+    if symmetric:
+        flags |= _lib.SK_SYMMETRIC
+        if no_diag:
+            flags |= _lib.SK_NO_DIAG
+    elif no_diag:
+        raise ValueError("no_diag needs symmetric=True")
+    sx, sy = _describe(X), _describe(Y)
+    if out is None:
+        out = torch.empty((nx, ny), dtype=torch.float32, device=dev)
+    nbytes = int(lib.sigkernel_workspace_bytes(_lib.SK_OP_GRAM, ctypes.byref(sx),
+                                               ctypes.byref(sy), dyadic_order, flags))
+    ws = _workspace(nbytes, dev, workspace)
+    st = lib.sigkernel_gram(ctypes.byref(sx), ctypes.byref(sy), int(dyadic_order), flags,
+                            out.data_ptr() if out.numel() else None, ws.data_ptr(),
+                            ws.numel() * ws.element_size(), _stream_ptr(dev))
+    _lib.check(st, "sigkernel_gram")
+    return out

@@ -1,0 +1,215 @@
+// C ABI of libsigkernel: argument validation, workspace layout, launches.
+// Declarations and contracts: include/sigkernel.h.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "../../include/sigkernel.h"
+#include "internal.h"
+
+namespace {
+
+using sk::Batch;
+
+constexpr int32_t kMaxDyadicOrder = 3;
+
+bool valid_batch(const sk_paths* p) {
+  if (!p) return false;
+  if (p->n_paths < 0 || p->dim < 1 || p->len < 1) return false;
+  return true;
+}
+
+Batch to_batch(const sk_paths* p) {
+  return Batch{p->points, p->offsets, p->n_paths, p->len, p->dim};
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// rows of the dense increment buffer of a batch (upper bound when ragged),
+// plus kStreamPad rows on each side that the streaming sweep may read
+size_t inc_rows(const sk_paths* p) {
+  return (size_t)p->n_paths * (size_t)(p->len - 1) + 2 * (size_t)sk::kStreamPad;
+}
+
+// Workspace of the forward call, in this order: dense increments of X and of
+// Y, then (ragged batches only) the per-path plan of X and of Y.
+struct ForwardLayout {
+  size_t incx, incy, planx_n, planx_start, plany_n, plany_start, total;
+};
+
+size_t plan_bytes_n(const sk_paths* p) {
+  return p->offsets ? align256((size_t)p->n_paths * sizeof(int32_t)) : 0;
+}
+size_t plan_bytes_start(const sk_paths* p) {
+  return p->offsets ? align256((size_t)p->n_paths * sizeof(int64_t)) : 0;
+}
+
+ForwardLayout forward_layout(const sk_paths* X, const sk_paths* Y) {
+  const size_t dp = (size_t)sk::padded_dim(X->dim);
+  ForwardLayout L{};
+  size_t off = 0;
+  L.incx = off;
+  off += align256(inc_rows(X) * dp * sizeof(float));
+  L.incy = off;
+  off += align256(inc_rows(Y) * dp * sizeof(float));
+  L.planx_n = off;
+  off += plan_bytes_n(X);
+  L.planx_start = off;
+  off += plan_bytes_start(X);
+  L.plany_n = off;
+  off += plan_bytes_n(Y);
+  L.plany_start = off;
+  off += plan_bytes_start(Y);
+  L.total = off;
+  return L;
+}
+
+size_t forward_ws(const sk_paths* X, const sk_paths* Y) { return forward_layout(X, Y).total; }
+
+// Pairs streamed through one wave for a Gram with a uniform y batch: enough
+// waves to fill every SIMD about four times, at most 64 pairs per run.
+int64_t choose_run(int64_t nx, int64_t ny) {
+  const char* env = getenv("SIGKERNEL_GRAM_RUN");
+  if (env) {
+    const long v = strtol(env, nullptr, 10);
+    if (v >= 1 && v <= 1024) return v;
+  }
+  const int64_t target_waves = 256 * 4 * 4;
+  int64_t run = (nx * ny) / target_waves;
+  if (run < 1) run = 1;
+  if (run > 64) run = 64;
+  if (run > ny) run = ny;
+  return run;
+}
+
+sk_status check_flags(uint32_t flags, uint32_t allowed) {
+  if (flags & ~allowed) return SK_ERR_FLAGS;
+  if ((flags & SK_NO_DIAG) && !(flags & SK_SYMMETRIC)) return SK_ERR_FLAGS;
+  return SK_OK;
+}
+
+sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t flags,
+                      float* out, void* ws, size_t ws_bytes, hipStream_t stream, int mode) {
+  const int d = X->dim;
+  const int dp = sk::padded_dim(d);
+  const int64_t fine_rows = (int64_t)(X->len - 1) << lam;
+  const int R = sk::choose_rows_per_lane(fine_rows < 1 ? 1 : fine_rows, lam, d);
+  if (R == 0) return SK_ERR_UNSUPPORTED;
+  const ForwardLayout L = forward_layout(X, Y);
+  if (ws_bytes < L.total) return SK_ERR_WORKSPACE;
+
+  char* base = static_cast<char*>(ws);
+  float* incx = reinterpret_cast<float*>(base + L.incx) + sk::kStreamPad * dp;
+  float* incy = reinterpret_cast<float*>(base + L.incy) + sk::kStreamPad * dp;
+  sk::PathPlan px{reinterpret_cast<int32_t*>(base + L.planx_n),
+                  reinterpret_cast<int64_t*>(base + L.planx_start)};
+  sk::PathPlan py{reinterpret_cast<int32_t*>(base + L.plany_n),
+                  reinterpret_cast<int64_t*>(base + L.plany_start)};
+  const sk::Batch bx = to_batch(X), by = to_batch(Y);
+  if (X->offsets && sk::launch_plan(bx, px, stream) != hipSuccess) return SK_ERR_HIP;
+  if (Y->offsets && sk::launch_plan(by, py, stream) != hipSuccess) return SK_ERR_HIP;
+  // h = G0 / 2^(2 lam + 1): fold the exact power-of-two scale into the x side
+  const float scale = ldexpf(1.0f, -(2 * lam + 1));
+  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, scale, dp, incx, stream) != hipSuccess)
+    return SK_ERR_HIP;
+  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream) != hipSuccess)
+    return SK_ERR_HIP;
+
+  sk::SweepArgs a{};
+  a.incx = incx;
+  a.incy = incy;
+  a.x_n = X->offsets ? px.n : nullptr;
+  a.x_start = X->offsets ? px.start : nullptr;
+  a.y_n = Y->offsets ? py.n : nullptr;
+  a.y_start = Y->offsets ? py.start : nullptr;
+  a.x_len = X->len;
+  a.y_len = Y->len;
+  a.nx = X->n_paths;
+  a.ny = Y->n_paths;
+  a.mode = mode;
+  a.no_diag = (flags & SK_NO_DIAG) ? 1 : 0;
+  a.out = out;
+  a.out_ld = Y->n_paths;
+  if (mode == 0) {
+    a.run = 1;
+    a.runs_per_row = 1;
+    a.n_waves = X->n_paths;
+  } else {
+    a.run = Y->offsets ? 1 : (int32_t)choose_run(X->n_paths, Y->n_paths);
+    a.runs_per_row = (Y->n_paths + a.run - 1) / a.run;
+    a.n_waves = X->n_paths * a.runs_per_row;
+  }
+  const hipError_t e = sk::launch_sweep(a, lam, R, d, stream);
+  if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;
+  return e == hipSuccess ? SK_OK : SK_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sigkernel_version(void) { return "0.1.0"; }
+
+const char* sigkernel_status_string(sk_status s) {
+  switch (s) {
+    case SK_OK: return "ok";
+    case SK_ERR_NULL: return "null pointer argument";
+    case SK_ERR_SHAPE: return "inconsistent shapes";
+    case SK_ERR_ORDER: return "unsupported dyadic order";
+    case SK_ERR_WORKSPACE: return "workspace missing or too small";
+    case SK_ERR_FLAGS: return "invalid flags";
+    case SK_ERR_HIP: return "HIP launch error";
+    case SK_ERR_UNSUPPORTED: return "shape outside the compiled configurations";
+    default: return "unknown status";
+  }
+}
+
+size_t sigkernel_workspace_bytes(int32_t op, const sk_paths* X, const sk_paths* Y,
+                                 int32_t dyadic_order, uint32_t flags) {
+  (void)dyadic_order;
+  (void)flags;
+  if (!valid_batch(X) || !valid_batch(Y)) return 0;
+  switch (op) {
+    case SK_OP_PAIR:
+    case SK_OP_GRAM:
+      return forward_ws(X, Y);
+    default:
+      return 0;
+  }
+}
+
+sk_status sigkernel_pair(const sk_paths* x, const sk_paths* y, int32_t dyadic_order,
+                         uint32_t flags, float* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!x || !y) return SK_ERR_NULL;
+  if (!valid_batch(x) || !valid_batch(y)) return SK_ERR_SHAPE;
+  if (!out && x->n_paths > 0) return SK_ERR_NULL;
+  if ((x->n_paths > 0 && !x->points) || (y->n_paths > 0 && !y->points)) return SK_ERR_NULL;
+  if (x->dim != y->dim || x->n_paths != y->n_paths) return SK_ERR_SHAPE;
+  if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (sk_status f = check_flags(flags, 0)) return f;
+  if (x->n_paths == 0) return SK_OK;
+  if (!ws) return SK_ERR_WORKSPACE;
+  return run_forward(x, y, dyadic_order, flags, out, ws, ws_bytes,
+                     static_cast<hipStream_t>(stream), 0);
+}
+
+sk_status sigkernel_gram(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
+                         uint32_t flags, float* K, void* ws, size_t ws_bytes, void* stream) {
+  if (!X || !Y) return SK_ERR_NULL;
+  if (!valid_batch(X) || !valid_batch(Y)) return SK_ERR_SHAPE;
+  if (!K && X->n_paths > 0 && Y->n_paths > 0) return SK_ERR_NULL;
+  if ((X->n_paths > 0 && !X->points) || (Y->n_paths > 0 && !Y->points)) return SK_ERR_NULL;
+  if (X->dim != Y->dim) return SK_ERR_SHAPE;
+  if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (sk_status f = check_flags(flags, SK_SYMMETRIC | SK_NO_DIAG)) return f;
+  if ((flags & SK_SYMMETRIC) &&
+      (X->points != Y->points || X->offsets != Y->offsets || X->n_paths != Y->n_paths ||
+       X->len != Y->len))
+    return SK_ERR_SHAPE;
+  if (X->n_paths == 0 || Y->n_paths == 0) return SK_OK;
+  if (!ws) return SK_ERR_WORKSPACE;
+  return run_forward(X, Y, dyadic_order, flags, K, ws, ws_bytes,
+                     static_cast<hipStream_t>(stream), (flags & SK_SYMMETRIC) ? 2 : 1);
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Increments of piecewise-linear paths (Section 3.1: on each coarse cell the
+// PDE coefficient is the inner product of the two segment increments), laid
+// out densely: the increments of consecutive paths are consecutive rows, so a
+// sweep that streams several y paths reads one contiguous row range.
+#include "internal.h"
+
+namespace sk {
+namespace {
+
+// Ragged batch plan: validate every path and prefix-sum the increment counts.
+// One workgroup of 1024 threads walks the paths in chunks with a running carry.
+__global__ __launch_bounds__(1024) void plan_kernel(const int64_t* __restrict__ off,
+                                                    int32_t len, int64_t n_paths,
+                                                    int32_t* __restrict__ n_out,
+                                                    int64_t* __restrict__ start_out) {
+  __shared__ int64_t warp_sums[16];
+  __shared__ int64_t carry_s;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t cap = n_paths * (int64_t)len;
+  for (int64_t base = 0; base < n_paths; base += 1024) {
+    const int64_t k = base + threadIdx.x;
+    int32_t n = 0;
+    if (k < n_paths) {
+      const int64_t s = off[k], e = off[k + 1], L = e - s;
+      const bool ok = s >= 0 && L >= 1 && L <= len && e <= cap;
+      n = ok ? (int32_t)(L - 1) : -1;
+      n_out[k] = n;
+    }
+    // inclusive scan of max(n, 0) within the wave, then across waves
+    int64_t v = n > 0 ? n : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t t = __shfl_up(v, o, 64);
+      if (lane >= o) v += t;
+    }
+    if (lane == 63) warp_sums[wid] = v;
+    __syncthreads();
+    int64_t before = carry_s;
+    for (int w = 0; w < wid; ++w) before += warp_sums[w];
+    const int64_t own = n > 0 ? n : 0;
+    if (k < n_paths) start_out[k] = before + v - own;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry_s = before + v;
+    __syncthreads();
+  }
+}
+
+// One workgroup per path: dense rows [start, start + n) of the output.
+__global__ __launch_bounds__(256) void increments_kernel(
+    const float* __restrict__ pts, const int64_t* __restrict__ off,
+    const int32_t* __restrict__ plan_n, const int64_t* __restrict__ plan_start, int32_t len,
+    int64_t n_paths, int32_t d, int32_t dpad, float scale, float* __restrict__ incr) {
+  const int64_t k = blockIdx.x;
+  if (k >= n_paths) return;
+  int64_t pstart, dstart;
+  int32_t n;
+  if (off) {
+    n = plan_n[k];
+    if (n <= 0) return;
+    pstart = off[k];
+    dstart = plan_start[k];
+  } else {
+    n = len - 1;
+    pstart = k * (int64_t)len;
+    dstart = k * (int64_t)n;
+  }
+  const int64_t total = (int64_t)n * dpad;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int64_t p = e / dpad;
+    const int c = (int)(e - p * dpad);
+    float v = 0.0f;
+    if (c < d) {
+      const float a = pts[(pstart + p + 1) * d + c];
+      const float b = pts[(pstart + p) * d + c];
+      v = (a - b) * scale;  // power-of-two scale: exact
+    }
+    incr[(dstart + p) * dpad + c] = v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_plan(const Batch& b, PathPlan plan, hipStream_t stream) {
+  if (b.n_paths == 0 || !b.offsets) return hipSuccess;
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, stream, b.offsets, b.len, b.n_paths,
+                     plan.n, plan.start);
+  return hipGetLastError();
+}
+
+hipError_t launch_increments(const Batch& b, const PathPlan* plan, float scale, int dpad,
+                             float* incr, hipStream_t stream) {
+  if (b.n_paths == 0 || (!b.offsets && b.len < 2)) return hipSuccess;
+  hipLaunchKernelGGL(increments_kernel, dim3((unsigned)b.n_paths), dim3(256), 0, stream,
+                     b.points, b.offsets, plan ? plan->n : nullptr,
+                     plan ? plan->start : nullptr, b.len, b.n_paths, b.dim, dpad, scale,
+                     incr);
+  return hipGetLastError();
+}
+
+}  // namespace sk

@@ -1,0 +1,75 @@
+// Internal declarations shared by the HIP translation units of libsigkernel.
+// Not part of the public ABI (see include/sigkernel.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sk {
+
+// Row pitch (floats) of the padded increment arrays: channels rounded up to a
+// multiple of 4 so that one row is a whole number of 16-byte loads.
+inline int padded_dim(int d) { return (d + 3) & ~3; }
+
+// A batch as the kernels see it: either uniform (offsets == nullptr, every path
+// has `len` points) or ragged (device offsets, `len` an upper bound).
+struct Batch {
+  const float* points;
+  const int64_t* offsets;
+  int64_t n_paths;
+  int32_t len;
+  int32_t dim;
+};
+
+// Per-path layout of the dense increment array of a ragged batch: n[k] is the
+// number of increments of path k (points - 1), or -1 when the path breaks the
+// batch contract; start[k] is its first row.  Rows of consecutive valid paths
+// are contiguous (start is the exclusive prefix sum of max(n, 0)).
+// Uniform batches use the closed form n = len - 1, start = k (len - 1).
+struct PathPlan {
+  int32_t* n;
+  int64_t* start;
+};
+
+hipError_t launch_plan(const Batch& b, PathPlan plan, hipStream_t stream);
+
+// Dense padded increments: row start[k] + p holds scale * (x_{p+1} - x_p),
+// p < n[k], zero-padded to `dpad` channels.  scale is a power of two.
+hipError_t launch_increments(const Batch& b, const PathPlan* plan, float scale, int dpad,
+                             float* incr, hipStream_t stream);
+
+// Work description of one forward sweep launch.
+struct SweepArgs {
+  const float* incx;        // dense increments of the x side, pre-scaled by 2^-(2 lam + 1)
+  const float* incy;        // dense increments of the y side
+  const int32_t* x_n;       // ragged plans (nullptr for a uniform batch)
+  const int64_t* x_start;
+  const int32_t* y_n;
+  const int64_t* y_start;
+  int32_t x_len, y_len;     // points per path of a uniform batch
+  int64_t nx, ny;           // paths per batch
+  int32_t mode;             // 0: pairs (x_k, y_k); 1: Gram; 2: Gram upper triangle, mirrored
+  int32_t no_diag;          // mode 2: diagonal written as 0
+  int32_t run;              // pairs streamed through one wave (Gram with uniform y)
+  int64_t runs_per_row;     // ceil(ny / run)
+  int64_t n_waves;
+  float* out;
+  int64_t out_ld;           // ny for the Gram
+};
+
+// Rows before and after the data of every dense increment buffer: a wave
+// streams rows g - lane for lanes 0..63 and prefetches two rows ahead, so it
+// reads rows -63 .. total + 66 of a run (steps are rounded up to a multiple
+// of three).
+constexpr int64_t kStreamPad = 128;
+
+// Largest number of fine rows per lane of the one-wave sweep.
+constexpr int kMaxRowsPerLane = 32;
+
+// Rows per lane for `fine_rows` rows on a 64-lane wave (0 if none is compiled).
+int choose_rows_per_lane(int64_t fine_rows, int lam, int dim);
+
+// Returns hipErrorInvalidValue when no compiled configuration covers the shape.
+hipError_t launch_sweep(const SweepArgs& a, int lam, int rows_per_lane, int dim,
+                        hipStream_t stream);
+
+}  // namespace sk

@@ -1,0 +1,127 @@
+"""C ABI contract checks that need no GPU.
+
+The library must load without a device, export every function that
+include/sigkernel.h declares, and reject bad arguments before it touches HIP
+(every error path below returns before any HIP call, so fake device pointers
+are safe here).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2006_14794_amd as sk
+from paper_2006_14794_amd import _lib
+from paper_2006_14794_amd._lib import SkPaths
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x10000  # never dereferenced: every call below fails validation first
+
+
+def header_functions():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            for m in re.finditer(r"^\s*[\w\s\*]+?\b(sigkernel_\w+)\s*\(", src, re.M):
+                names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = _lib.load()
+    declared = header_functions()
+    assert "sigkernel_gram" in declared and "sigkernel_pair" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(_lib.EXPORTED)
+
+
+def test_status_strings():
+    for code in range(-7, 1):
+        s = sk.status_string(code)
+        assert isinstance(s, str) and s
+    assert sk.status_string(123) == "unknown status"
+    assert sk.version().count(".") == 2
+
+
+def paths(n=4, L=16, d=3, pts=FAKE, off=None):
+    return SkPaths(pts, off, n, L, d)
+
+
+def call_gram(X, Y, lam=1, flags=0, K=FAKE, ws=FAKE, nbytes=1 << 30):
+    lib = _lib.load()
+    return lib.sigkernel_gram(ctypes.byref(X) if X is not None else None,
+                              ctypes.byref(Y) if Y is not None else None,
+                              lam, flags, K, ws, nbytes, None)
+
+
+def call_pair(x, y, lam=1, flags=0, out=FAKE, ws=FAKE, nbytes=1 << 30):
+    lib = _lib.load()
+    return lib.sigkernel_pair(ctypes.byref(x), ctypes.byref(y), lam, flags, out, ws, nbytes,
+                              None)
+
+
+def test_null_arguments():
+    assert call_gram(None, paths()) == _lib.SK_ERR_NULL
+    assert call_gram(paths(), paths(), K=None) == _lib.SK_ERR_NULL
+    assert call_gram(paths(pts=None), paths()) == _lib.SK_ERR_NULL
+    assert call_pair(paths(), paths(), out=None) == _lib.SK_ERR_NULL
+
+
+def test_shape_errors():
+    assert call_gram(paths(d=3), paths(d=4)) == _lib.SK_ERR_SHAPE
+    assert call_gram(paths(d=0), paths(d=0)) == _lib.SK_ERR_SHAPE
+    assert call_gram(paths(L=0), paths()) == _lib.SK_ERR_SHAPE
+    assert call_gram(paths(n=-1), paths()) == _lib.SK_ERR_SHAPE
+    assert call_pair(paths(n=3), paths(n=4)) == _lib.SK_ERR_SHAPE
+
+
+def test_order_and_flag_errors():
+    assert call_gram(paths(), paths(), lam=-1) == _lib.SK_ERR_ORDER
+    assert call_gram(paths(), paths(), lam=4) == _lib.SK_ERR_ORDER
+    assert call_gram(paths(), paths(), flags=1 << 20) == _lib.SK_ERR_FLAGS
+    assert call_gram(paths(), paths(), flags=_lib.SK_NO_DIAG) == _lib.SK_ERR_FLAGS
+    # symmetric needs X and Y to be the same batch
+    X, Y = paths(pts=FAKE), paths(pts=FAKE * 2)
+    assert call_gram(X, Y, flags=_lib.SK_SYMMETRIC) == _lib.SK_ERR_SHAPE
+    assert call_pair(paths(), paths(), flags=_lib.SK_SYMMETRIC) == _lib.SK_ERR_FLAGS
+
+
+def test_workspace_errors_and_sizing():
+    lib = _lib.load()
+    X, Y = paths(n=4, L=16, d=3), paths(n=5, L=9, d=3)
+    need = lib.sigkernel_workspace_bytes(_lib.SK_OP_GRAM, ctypes.byref(X), ctypes.byref(Y), 1, 0)
+    # dense padded increments: 4 floats per segment of each batch plus 64 rows
+    # on each side, 256-byte aligned
+    assert need == (256 * ((4 * (4 * 15 + 256) * 4 + 255) // 256)
+                    + 256 * ((4 * (5 * 8 + 256) * 4 + 255) // 256))
+    # ragged batches add a per-path plan (int32 count + int64 start)
+    Xr = paths(n=4, L=16, d=3, off=FAKE)
+    need_r = lib.sigkernel_workspace_bytes(_lib.SK_OP_GRAM, ctypes.byref(Xr), ctypes.byref(Y), 1, 0)
+    assert need_r == need + 256 + 256
+    assert call_gram(X, Y, ws=None) == _lib.SK_ERR_WORKSPACE
+    assert call_gram(X, Y, nbytes=need - 1) == _lib.SK_ERR_WORKSPACE
+    bad = paths(d=0)
+    assert lib.sigkernel_workspace_bytes(_lib.SK_OP_GRAM, ctypes.byref(bad), ctypes.byref(Y), 1,
+                                         0) == 0
+
+
+def test_empty_batches_are_no_ops():
+    assert call_gram(paths(n=0), paths(n=3), K=None, ws=None) == _lib.SK_OK
+    assert call_pair(paths(n=0), paths(n=0), out=None, ws=None) == _lib.SK_OK
+
+
+def test_unsupported_shapes_are_reported():
+    # 64 lanes x 32 rows per lane is the longest x side of the one-wave sweep
+    X = paths(n=2, L=64 * 32 // 8 + 2, d=16)
+    assert call_gram(X, paths(n=2, L=8, d=16), lam=3) == _lib.SK_ERR_UNSUPPORTED
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        _lib.load()
