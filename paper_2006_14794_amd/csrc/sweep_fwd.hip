@@ -154,8 +154,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
   // every pair of a run has the same width (runs longer than one pair are
   // only formed for uniform y batches)
   const int32_t cn = n_inc(a.y_n, a.y_len, b0);
-  int32_t q = 0;
-  int64_t cb = b0;
+  int32_t q = 0;  // column of the current pair
 
   double u[R];
 #pragma unroll
@@ -194,11 +193,6 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     for (int cc = 0; cc < S; ++cc) up[cc] = from_prev_lane(pub[cc], up[cc]);
 
     if ((uint32_t)g < (uint32_t)total32) {
-      if (q == 0) {  // first column of a pair: left boundary
-#pragma unroll
-        for (int r = 0; r < R; ++r) u[r] = 1.0;
-        up_last = 1.0;
-      }
       double gk[CR];
 #pragma unroll
       for (int c = 0; c < CR; ++c) gk[c] = 1.0 + (double)h32[c];
@@ -223,16 +217,22 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
 #pragma unroll
       for (int cc = 0; cc < S; ++cc) pub[cc] = v[R - 1][cc];
       up_last = up[S - 1];
-      const bool last = (q == cn - 1);
-      if (last && lane == end_lane) {
-        double fv = 1.0;
+      if (++q == cn) {
+        // last column of a pair: emit its terminal value, then the left
+        // boundary (value 1) of the next pair of the run
+        if (lane == end_lane) {
+          double fv = 1.0;
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-          if (r == end_r) fv = u[r];
-        store_out(a, ia, cb, (a.mode == 2 && a.no_diag && cb == ia) ? 0.0f : (float)fv);
+          for (int r = 0; r < R; ++r)
+            if (r == end_r) fv = u[r];
+          const int64_t cb = b0 + g / cn;
+          store_out(a, ia, cb, (a.mode == 2 && a.no_diag && cb == ia) ? 0.0f : (float)fv);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = 1.0;
+        up_last = 1.0;
+        q = 0;
       }
-      q = last ? 0 : q + 1;
-      cb += last ? 1 : 0;
     }
     ++g;
     yp += DP;
