@@ -103,6 +103,30 @@ sk_status sigkernel_gram(const sk_paths *X, const sk_paths *Y, int32_t dyadic_or
                          uint32_t flags, float *K, void *ws, size_t ws_bytes,
                          void *stream);
 
+/*
+ * sigkernel_gram_backward -- gradient of a weighted sum of Gram entries,
+ *   L = sum_{a,b} dK[a][b] k_hat(X_a, Y_b),
+ * with respect to every point of X and of Y:
+ *   dX[a] = sum_b dK[a][b] d k_hat(X_a, Y_b) / d X_a   (overwritten),
+ *   dY[b] = sum_a dK[a][b] d k_hat(X_a, Y_b) / d Y_b   (overwritten).
+ * The derivative is that of the discrete scheme (eq. (explicit_finite_diff)
+ * on P_lambda, the paper gives none): reverse accumulation through the cell
+ * recurrence, then through the increment inner products of Section 3.1 and
+ * the increments x_{p+1} - x_p.
+ *  - dK: DEVICE float[X->n_paths * Y->n_paths], row-major; dX / dY: DEVICE
+ *    float shaped like the points; either may be NULL (not wanted).
+ *  - SK_SYMMETRIC: Y is X and the Gram is symmetric; the gradient of
+ *    sum dK[a][b] K[a][b] over all (a, b) goes to dX and dY must be NULL.
+ *    With SK_NO_DIAG as well, the diagonal entries (the constant 0 of the
+ *    forward) carry no gradient.
+ *  - Uniform batches only (ragged offsets give SK_ERR_UNSUPPORTED).
+ *  - Workspace: sigkernel_workspace_bytes(SK_OP_GRAM_BACKWARD, ...); the
+ *    forward cell sums of at most 4 GiB worth of pairs are stored at a time.
+ */
+sk_status sigkernel_gram_backward(const sk_paths *X, const sk_paths *Y, int32_t dyadic_order,
+                                  uint32_t flags, const float *dK, float *dX, float *dY,
+                                  void *ws, size_t ws_bytes, void *stream);
+
 /* Workspace sizing.  op is one of the SK_OP_* values. */
 enum { SK_OP_PAIR = 0, SK_OP_GRAM = 1, SK_OP_GRAM_BACKWARD = 2 };
 size_t sigkernel_workspace_bytes(int32_t op, const sk_paths *X, const sk_paths *Y,

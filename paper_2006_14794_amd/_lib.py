@@ -33,6 +33,7 @@ SK_OP_GRAM_BACKWARD = 2
 EXPORTED = (
     "sigkernel_pair",
     "sigkernel_gram",
+    "sigkernel_gram_backward",
     "sigkernel_workspace_bytes",
     "sigkernel_status_string",
     "sigkernel_version",
@@ -75,6 +76,8 @@ def load():
     lib.sigkernel_pair.restype = i32
     lib.sigkernel_gram.argtypes = [P, P, i32, u32, vp, vp, sz, vp]
     lib.sigkernel_gram.restype = i32
+    lib.sigkernel_gram_backward.argtypes = [P, P, i32, u32, vp, vp, vp, vp, sz, vp]
+    lib.sigkernel_gram_backward.restype = i32
     lib.sigkernel_workspace_bytes.argtypes = [i32, P, P, i32, u32]
     lib.sigkernel_workspace_bytes.restype = sz
     lib.sigkernel_status_string.argtypes = [i32]

@@ -149,3 +149,85 @@ def sigkernel_gram(X: PathsLike, Y: Optional[PathsLike] = None, dyadic_order: in
                             ws.numel() * ws.element_size(), _stream_ptr(dev))
     _lib.check(st, "sigkernel_gram")
     return out
+
+
+def sigkernel_gram_backward(X: torch.Tensor, Y: Optional[torch.Tensor], dK: torch.Tensor,
+                            dyadic_order: int = 0, *, symmetric: bool = False,
+                            no_diag: bool = False, need_x: bool = True, need_y: bool = True,
+                            workspace: Optional[torch.Tensor] = None):
+    """(dX, dY) = gradients of sum(dK * K) with respect to the points of X and
+    Y (either None when not wanted).  With ``symmetric=True`` Y must be None
+    or X itself and the whole gradient is returned as dX (dY is None)."""
+    lib = _lib.load()
+    if Y is None:
+        Y = X
+    if symmetric and Y is not X:
+        raise ValueError("symmetric Gram needs Y to be X")
+    if no_diag and not symmetric:
+        raise ValueError("no_diag needs symmetric=True")
+    dev = _device(X)
+    flags = 0
+    if symmetric:
+        flags |= _lib.SK_SYMMETRIC | (_lib.SK_NO_DIAG if no_diag else 0)
+        need_y = False
+    sx, sy = _describe(X), _describe(Y)
+    if dK.dtype != torch.float32 or not dK.is_cuda:
+        raise TypeError("dK must be a float32 device tensor")
+    dK = dK.contiguous()
+    if dK.shape != (_n_paths(X), _n_paths(Y)):
+        raise ValueError("dK must be [X.n_paths, Y.n_paths]")
+    dX = torch.empty_like(X) if need_x else None
+    dY = torch.empty_like(Y) if need_y else None
+    nbytes = int(lib.sigkernel_workspace_bytes(_lib.SK_OP_GRAM_BACKWARD, ctypes.byref(sx),
+                                               ctypes.byref(sy), int(dyadic_order), flags))
+    ws = _workspace(nbytes, dev, workspace)
+    st = lib.sigkernel_gram_backward(ctypes.byref(sx), ctypes.byref(sy), int(dyadic_order), flags,
+                                     dK.data_ptr(), dX.data_ptr() if dX is not None else None,
+                                     dY.data_ptr() if dY is not None else None, ws.data_ptr(),
+                                     ws.numel() * ws.element_size(), _stream_ptr(dev))
+    _lib.check(st, "sigkernel_gram_backward")
+    return dX, dY
+
+
+class SigKernelGram(torch.autograd.Function):
+    """K = sigkernel_gram(X, Y); backward through sigkernel_gram_backward."""
+
+    @staticmethod
+    def forward(ctx, X, Y, dyadic_order):
+        ctx.dyadic_order = dyadic_order
+        ctx.save_for_backward(X, Y)
+        return sigkernel_gram(X, Y, dyadic_order)
+
+    @staticmethod
+    def backward(ctx, dK):
+        X, Y = ctx.saved_tensors
+        dX, dY = sigkernel_gram_backward(X, Y, dK.to(torch.float32), ctx.dyadic_order,
+                                         need_x=ctx.needs_input_grad[0],
+                                         need_y=ctx.needs_input_grad[1])
+        return dX, dY, None
+
+
+class SigKernelGramSymmetric(torch.autograd.Function):
+    """K = sigkernel_gram(X, X, symmetric=True, no_diag=...) with its gradient."""
+
+    @staticmethod
+    def forward(ctx, X, dyadic_order, no_diag):
+        ctx.dyadic_order = dyadic_order
+        ctx.no_diag = no_diag
+        ctx.save_for_backward(X)
+        return sigkernel_gram(X, None, dyadic_order, symmetric=True, no_diag=no_diag)
+
+    @staticmethod
+    def backward(ctx, dK):
+        (X,) = ctx.saved_tensors
+        dX, _ = sigkernel_gram_backward(X, None, dK.to(torch.float32), ctx.dyadic_order,
+                                        symmetric=True, no_diag=ctx.no_diag)
+        return dX, None, None
+
+
+def gram(X: torch.Tensor, Y: Optional[torch.Tensor] = None, dyadic_order: int = 0, *,
+         no_diag: bool = False) -> torch.Tensor:
+    """Differentiable Gram matrix; Y None means the symmetric Gram of X."""
+    if Y is None:
+        return SigKernelGramSymmetric.apply(X, dyadic_order, no_diag)
+    return SigKernelGram.apply(X, Y, dyadic_order)

@@ -82,6 +82,47 @@ int64_t choose_run(int64_t nx, int64_t ny) {
   return run;
 }
 
+// Backward workspace: the forward layout, then the per-wave store of one
+// chunk of waves, the per-run x-side and per-pair y-side increment gradients.
+constexpr size_t kStoreCapBytes = size_t(4) << 30;
+
+struct BackwardPlan {
+  int R;
+  int64_t run, runs_per_row, n_waves;
+  int64_t store_stride;  // floats per wave
+  int64_t chunk;         // waves per chunk
+  size_t store_off, partx_off, party_off, total;
+};
+
+BackwardPlan backward_plan(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t flags) {
+  BackwardPlan P{};
+  const int64_t m = X->len - 1, n = Y->len - 1;
+  const int64_t fine_rows = m << lam;
+  P.R = sk::choose_rows_per_lane(fine_rows < 1 ? 1 : fine_rows, lam, X->dim);
+  P.run = choose_run(X->n_paths, Y->n_paths);
+  P.runs_per_row = (Y->n_paths + P.run - 1) / P.run;
+  P.n_waves = X->n_paths * P.runs_per_row;
+  const int64_t rs = (int64_t)P.R << lam;
+  P.store_stride = sk::sweep_steps(P.run * (n > 0 ? n : 1)) * 64 * rs;
+  const int64_t per_wave = P.store_stride * (int64_t)sizeof(float);
+  P.chunk = (int64_t)(kStoreCapBytes / (size_t)per_wave);
+  if (P.chunk < 1) P.chunk = 1;
+  if (P.chunk > P.n_waves) P.chunk = P.n_waves;
+  size_t off = forward_ws(X, Y);
+  P.store_off = off;
+  off += align256((size_t)P.chunk * (size_t)per_wave);
+  P.partx_off = off;
+  off += align256((size_t)P.n_waves * (size_t)(m > 0 ? m : 0) * X->dim * sizeof(float));
+  P.party_off = off;
+  off += align256((size_t)X->n_paths * Y->n_paths * (size_t)(n > 0 ? n : 0) * X->dim *
+                  sizeof(float));
+  P.total = off;
+  (void)flags;
+  return P;
+}
+
+
+
 sk_status check_flags(uint32_t flags, uint32_t allowed) {
   if (flags & ~allowed) return SK_ERR_FLAGS;
   if ((flags & SK_NO_DIAG) && !(flags & SK_SYMMETRIC)) return SK_ERR_FLAGS;
@@ -173,6 +214,9 @@ size_t sigkernel_workspace_bytes(int32_t op, const sk_paths* X, const sk_paths* 
     case SK_OP_PAIR:
     case SK_OP_GRAM:
       return forward_ws(X, Y);
+    case SK_OP_GRAM_BACKWARD:
+      if (X->offsets || Y->offsets || X->dim != Y->dim) return 0;
+      return backward_plan(X, Y, dyadic_order, flags).total;
     default:
       return 0;
   }
@@ -210,6 +254,106 @@ sk_status sigkernel_gram(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
   if (!ws) return SK_ERR_WORKSPACE;
   return run_forward(X, Y, dyadic_order, flags, K, ws, ws_bytes,
                      static_cast<hipStream_t>(stream), (flags & SK_SYMMETRIC) ? 2 : 1);
+}
+
+sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
+                                  uint32_t flags, const float* dK, float* dX, float* dY, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  if (!X || !Y) return SK_ERR_NULL;
+  if (!valid_batch(X) || !valid_batch(Y)) return SK_ERR_SHAPE;
+  if (X->dim != Y->dim) return SK_ERR_SHAPE;
+  if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (sk_status f = check_flags(flags, SK_SYMMETRIC | SK_NO_DIAG)) return f;
+  const bool sym = (flags & SK_SYMMETRIC) != 0;
+  if (sym && (X->points != Y->points || X->offsets != Y->offsets || X->n_paths != Y->n_paths ||
+              X->len != Y->len))
+    return SK_ERR_SHAPE;
+  if (sym && dY) return SK_ERR_SHAPE;  // one batch: its gradient goes to dX
+  if (X->offsets || Y->offsets) return SK_ERR_UNSUPPORTED;
+  if (X->n_paths == 0 || Y->n_paths == 0) return SK_OK;
+  if (!dK || (!dX && !dY)) return SK_ERR_NULL;
+  if ((X->n_paths > 0 && !X->points) || (Y->n_paths > 0 && !Y->points)) return SK_ERR_NULL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int lam = dyadic_order;
+  const int d = X->dim;
+  // one-point paths: the kernel is the constant 1, every gradient is 0
+  if (X->len < 2 || Y->len < 2) {
+    if (dX && sk::launch_fill(dX, X->n_paths * X->len * d, 0.0f, st) != hipSuccess)
+      return SK_ERR_HIP;
+    if (dY && sk::launch_fill(dY, Y->n_paths * Y->len * d, 0.0f, st) != hipSuccess)
+      return SK_ERR_HIP;
+    return SK_OK;
+  }
+  const BackwardPlan P = backward_plan(X, Y, lam, flags);
+  if (P.R == 0 || !sk::adjoint_supported(P.R, lam, d)) return SK_ERR_UNSUPPORTED;
+  if (!ws) return SK_ERR_WORKSPACE;
+  if (ws_bytes < P.total) return SK_ERR_WORKSPACE;
+
+  const int dp = sk::padded_dim(d);
+  const ForwardLayout L = forward_layout(X, Y);
+  char* base = static_cast<char*>(ws);
+  float* incx = reinterpret_cast<float*>(base + L.incx) + sk::kStreamPad * dp;
+  float* incy = reinterpret_cast<float*>(base + L.incy) + sk::kStreamPad * dp;
+  float* store = reinterpret_cast<float*>(base + P.store_off);
+  float* part_x = reinterpret_cast<float*>(base + P.partx_off);
+  float* part_y = reinterpret_cast<float*>(base + P.party_off);
+  const sk::Batch bx = to_batch(X), by = to_batch(Y);
+  const float scale = ldexpf(1.0f, -(2 * lam + 1));
+  if (sk::launch_increments(bx, nullptr, scale, dp, incx, st) != hipSuccess) return SK_ERR_HIP;
+  if (sk::launch_increments(by, nullptr, 1.0f, dp, incy, st) != hipSuccess) return SK_ERR_HIP;
+
+  sk::SweepArgs fa{};
+  fa.incx = incx;
+  fa.incy = incy;
+  fa.x_len = X->len;
+  fa.y_len = Y->len;
+  fa.nx = X->n_paths;
+  fa.ny = Y->n_paths;
+  fa.mode = sym ? 2 : 1;
+  fa.no_diag = 0;
+  fa.run = (int32_t)P.run;
+  fa.runs_per_row = P.runs_per_row;
+  fa.out = nullptr;
+  fa.out_ld = Y->n_paths;
+  fa.store = store;
+  fa.store_stride = P.store_stride;
+
+  sk::BwdArgs ba{};
+  ba.incx = incx;
+  ba.incy = incy;
+  ba.x_len = X->len;
+  ba.y_len = Y->len;
+  ba.nx = X->n_paths;
+  ba.ny = Y->n_paths;
+  ba.mode = sym ? 2 : 1;
+  ba.no_diag = (flags & SK_NO_DIAG) ? 1 : 0;
+  ba.run = (int32_t)P.run;
+  ba.runs_per_row = P.runs_per_row;
+  ba.dK = dK;
+  ba.store = store;
+  ba.store_stride = P.store_stride;
+  ba.part_x = part_x;
+  ba.part_y = part_y;
+  for (int64_t w0 = 0; w0 < P.n_waves; w0 += P.chunk) {
+    const int64_t nw = (P.n_waves - w0) < P.chunk ? (P.n_waves - w0) : P.chunk;
+    fa.wave0 = w0;
+    fa.n_waves = nw;
+    if (sk::launch_sweep_store(fa, lam, P.R, d, st) != hipSuccess) return SK_ERR_HIP;
+    ba.wave0 = w0;
+    ba.n_waves = nw;
+    if (sk::launch_adjoint(ba, lam, P.R, d, st) != hipSuccess) return SK_ERR_HIP;
+  }
+  if (dX) {
+    if (sk::launch_point_grad(part_x, P.runs_per_row, scale, sym ? part_y : nullptr, X->n_paths,
+                              Y->n_paths, sym, X->n_paths, X->len, d, dX, st) != hipSuccess)
+      return SK_ERR_HIP;
+  }
+  if (dY) {
+    if (sk::launch_point_grad(nullptr, 0, 1.0f, part_y, X->n_paths, Y->n_paths, false,
+                              Y->n_paths, Y->len, d, dY, st) != hipSuccess)
+      return SK_ERR_HIP;
+  }
+  return SK_OK;
 }
 
 }  // extern "C"

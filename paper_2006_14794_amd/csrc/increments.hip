@@ -80,7 +80,21 @@ __global__ __launch_bounds__(256) void increments_kernel(
   }
 }
 
+__global__ __launch_bounds__(256) void fill_kernel(float* __restrict__ p, int64_t n, float v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 }  // namespace
+
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, v);
+  return hipGetLastError();
+}
 
 hipError_t launch_plan(const Batch& b, PathPlan plan, hipStream_t stream) {
   if (b.n_paths == 0 || !b.offsets) return hipSuccess;

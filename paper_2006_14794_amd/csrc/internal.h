@@ -32,6 +32,10 @@ struct PathPlan {
 
 hipError_t launch_plan(const Batch& b, PathPlan plan, hipStream_t stream);
 
+// p[0 .. n) = v (a kernel rather than a memset node, so that captured graphs
+// replay it like any other launch)
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t stream);
+
 // Dense padded increments: row start[k] + p holds scale * (x_{p+1} - x_p),
 // p < n[k], zero-padded to `dpad` channels.  scale is a power of two.
 hipError_t launch_increments(const Batch& b, const PathPlan* plan, float scale, int dpad,
@@ -52,8 +56,13 @@ struct SweepArgs {
   int32_t run;              // pairs streamed through one wave (Gram with uniform y)
   int64_t runs_per_row;     // ceil(ny / run)
   int64_t n_waves;
-  float* out;
+  float* out;               // nullptr: terminal values not written
   int64_t out_ld;           // ny for the Gram
+  // waves [wave0, wave0 + n_waves) of the run enumeration are launched
+  int64_t wave0;
+  // adjoint support: per wave, nsteps x 64 lanes x (R 2^lam) floats
+  float* store;
+  int64_t store_stride;
 };
 
 // Rows before and after the data of every dense increment buffer: a wave
@@ -71,5 +80,39 @@ int choose_rows_per_lane(int64_t fine_rows, int lam, int dim);
 // Returns hipErrorInvalidValue when no compiled configuration covers the shape.
 hipError_t launch_sweep(const SweepArgs& a, int lam, int rows_per_lane, int dim,
                         hipStream_t stream);
+hipError_t launch_sweep_store(const SweepArgs& a, int lam, int rows_per_lane, int dim,
+                              hipStream_t stream);
+
+// Adjoint sweep of a Gram batch (uniform batches).
+struct BwdArgs {
+  const float* incx;        // dense x increments, pre-scaled by 2^-(2 lam + 1)
+  const float* incy;        // dense y increments
+  int32_t x_len, y_len;     // points per path (both >= 2)
+  int64_t nx, ny;
+  int32_t mode;             // 1: Gram; 2: upper triangle of a symmetric Gram
+  int32_t no_diag;          // mode 2: diagonal pairs carry no gradient
+  int32_t run;
+  int64_t runs_per_row;
+  int64_t wave0, n_waves;   // waves launched
+  const float* dK;          // upstream weights [nx][ny]
+  const float* store;       // forward S values of the launched waves
+  int64_t store_stride;     // floats per wave
+  float* part_x;            // [all waves][x_len - 1][dim]: x-side increment gradients per run
+  float* part_y;            // [nx][ny][y_len - 1][dim]: y-side increment gradients per pair
+};
+
+hipError_t launch_adjoint(const BwdArgs& a, int lam, int rows_per_lane, int dim,
+                          hipStream_t stream);
+bool adjoint_supported(int rows_per_lane, int lam, int dim);
+hipError_t launch_point_grad(const float* part_x, int64_t runs_per_row, float scale,
+                             const float* part_y, int64_t part_y_rows, int64_t part_y_ld,
+                             bool col_upper, int64_t n_paths, int32_t len, int32_t d, float* out,
+                             hipStream_t stream);
+
+// Steps of a wave that streams `total` coarse columns (a multiple of three:
+// the y-row prefetch rotates three buffers).
+__host__ __device__ inline int64_t sweep_steps(int64_t total) {
+  return ((total + 63 + 2) / 3) * 3;
+}
 
 }  // namespace sk

@@ -1,323 +1,33 @@
-// Forward sweep of the explicit Goursat scheme, Section 3.1,
-// eq. (explicit_finite_diff), on the dyadic grid P_lambda, with the coarse
-// increment inner products computed on the fly.
-//
-// Mapping (one 64-lane wavefront per run of pairs that share the x path):
-//   * lane l owns the R consecutive fine cell rows [l R, l R + R) of the grid
-//     (rows follow x) and keeps their current values in registers;
-//   * the wave advances one coarse column (2^lambda fine columns) per step,
-//     lane l lagging lane l-1 by one step, so that the cells being updated lie
-//     on one block antidiagonal (the antidiagonal independence noted in
-//     Section 3.1.1);
-//   * lane l-1's bottom-row values at the current coarse column arrive through
-//     one DPP wave_shr:1 move per fine column (two 32-bit moves per double);
-//   * the y increments of consecutive pairs are consecutive rows, so a wave
-//     streams the columns of several pairs (x_a, y_b), (x_a, y_{b+1}), ...
-//     back to back and pays the 63-step pipeline fill once per run; a lane
-//     that reaches the first column of the next pair resets its rows to the
-//     boundary value 1;
-//   * the coarse coefficient G0[p][q] = <dx_p, dy_q> is recomputed per step
-//     from the lane's dx rows (registers, pre-scaled by 2^-(2 lambda + 1)) and
-//     the coarse column's dy row (loaded two steps ahead), and reused for the
-//     4^lambda fine cells it covers (remark after eq. (explicit_finite_diff)).
-//
-// Cell update, in double: with A = left, B = up, C = up-left node and
-// g = 1 + G0 / 2^(2 lambda + 1),
-//     K' = fma(g, A + B, -C)  ==  A + B - C + (g - 1)(A + B),
-// two double operations per cell.  g is formed in double, where the rounding
-// of 1 + h perturbs h by at most 2^-53 in absolute value.
-#include <math.h>
-
-#include "internal.h"
+// Forward sweep launches (value only).  Kernel: sweep_fwd_kernel.h.
+#include "dispatch.h"
+#include "sweep_fwd_kernel.h"
 
 namespace sk {
 namespace {
 
-// lane l receives lane l-1's value; lane 0 keeps `keep` (wave_shr:1 with the
-// bound control off leaves the out-of-range lane's destination untouched).
-__device__ __forceinline__ double from_prev_lane(double v, double keep) {
-  const unsigned long long bv = (unsigned long long)__double_as_longlong(v);
-  const unsigned long long bk = (unsigned long long)__double_as_longlong(keep);
-  const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)bk, (int)(unsigned)bv, 0x138, 0xF,
-                                             0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(bk >> 32),
-                                             (int)(unsigned)(bv >> 32), 0x138, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
-                                          (unsigned long long)(unsigned)lo));
-}
-
-template <int DP>
-__device__ __forceinline__ void load_row(const float* __restrict__ p, float (&v)[DP]) {
-  const float4* p4 = reinterpret_cast<const float4*>(p);
-#pragma unroll
-  for (int c = 0; c < DP / 4; ++c) {
-    const float4 t = p4[c];
-    v[4 * c + 0] = t.x;
-    v[4 * c + 1] = t.y;
-    v[4 * c + 2] = t.z;
-    v[4 * c + 3] = t.w;
-  }
-}
-
-__device__ __forceinline__ int32_t n_inc(const int32_t* plan, int32_t len, int64_t k) {
-  return plan ? plan[k] : len - 1;
-}
-__device__ __forceinline__ int64_t first_row(const int64_t* plan, int32_t len, int64_t k) {
-  return plan ? plan[k] : k * (int64_t)(len - 1);
-}
-
-__device__ __forceinline__ void store_out(const SweepArgs& a, int64_t ia, int64_t ib, float v) {
-  if (a.mode == 0) {
-    a.out[ia] = v;
-  } else {
-    a.out[ia * a.out_ld + ib] = v;
-    if (a.mode == 2 && ia != ib) a.out[ib * a.out_ld + ia] = v;
-  }
-}
-
-template <int R, int LAM, int D>
-__global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
-  constexpr int DP = (D + 3) & ~3;
-  constexpr int S = 1 << LAM;                          // fine columns per coarse column
-  constexpr int CR = (R >> LAM) > 0 ? (R >> LAM) : 1;  // coarse rows per lane
-
-  const int lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (w >= a.n_waves) return;  // uniform per wave
-
-  // ---- the run of pairs of this wave -------------------------------------
-  int64_t ia, b0, b1;
-  if (a.mode == 0) {
-    ia = w;
-    b0 = w;
-    b1 = w + 1;
-  } else {
-    ia = w / a.runs_per_row;
-    b0 = (w - ia * a.runs_per_row) * a.run;
-    b1 = b0 + a.run < a.ny ? b0 + a.run : a.ny;
-    if (a.mode == 2 && b0 < ia) b0 = ia;
-    if (b0 >= b1) return;
-  }
-  const int32_t m = n_inc(a.x_n, a.x_len, ia);
-
-  // Pairs with nothing to sweep: a broken path (NaN), the diagonal of an
-  // unbiased Gram (0), a one-point path (boundary value 1).  The stream below
-  // gives such pairs zero columns.
-  int64_t total = 0;
-  for (int64_t b = b0; b < b1; ++b) {
-    const int32_t nb = n_inc(a.y_n, a.y_len, b);
-    float v = 0.0f;
-    bool trivial = true;
-    if (m < 0 || nb < 0)
-      v = __builtin_nanf("");
-    else if (m == 0 || nb == 0)
-      v = 1.0f;
+struct FwdPlain {
+  using Fn = void (*)(const SweepArgs);
+  template <int R, int LAM, int D>
+  static Fn get() {
+    if constexpr (sweep_fits(R, LAM, D))
+      return &fwd::sweep_kernel<R, LAM, D, false>;
     else
-      trivial = false;
-    if (!trivial) {
-      total += nb;
-    } else if (lane == 0) {
-      store_out(a, ia, b, v);
-    }
+      return nullptr;
   }
-  if (m <= 0 || total == 0) return;
-  const int M = m << LAM;
-  if (M > 64 * R) {  // excluded by the host; never read past the lane rows
-    for (int64_t b = b0 + lane; b < b1; b += 64) store_out(a, ia, b, __builtin_nanf(""));
-    return;
-  }
-
-  const int row0 = lane * R;
-  const int p0 = row0 >> LAM;
-  const int64_t xrow = first_row(a.x_start, a.x_len, ia);
-  float dx[CR][D];
-#pragma unroll
-  for (int c = 0; c < CR; ++c) {
-    float t[DP];
-    if (p0 + c < m) {
-      load_row<DP>(a.incx + (xrow + p0 + c) * DP, t);
-    } else {
-#pragma unroll
-      for (int k = 0; k < DP; ++k) t[k] = 0.0f;
-    }
-#pragma unroll
-    for (int k = 0; k < D; ++k) dx[c][k] = t[k];
-  }
-
-  // y stream: global column g of the run is dense row first_row(b0) + g.  The
-  // increment buffers carry kStreamPad rows before and after the data, so
-  // rows g in [-63, total + 3] can be read without clamping (rows outside
-  // the run only feed lanes that are inactive at that step).
-  const int32_t total32 = (int32_t)total;
-  int32_t g = -lane;
-  const float* __restrict__ yp = a.incy + (first_row(a.y_start, a.y_len, b0) + g) * DP;
-  // every pair of a run has the same width (runs longer than one pair are
-  // only formed for uniform y batches)
-  const int32_t cn = n_inc(a.y_n, a.y_len, b0);
-  int32_t q = 0;  // column of the current pair
-
-  double u[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) u[r] = 1.0;
-  double pub[S], up[S];
-#pragma unroll
-  for (int cc = 0; cc < S; ++cc) {
-    pub[cc] = 1.0;
-    up[cc] = 1.0;  // lane 0 keeps the boundary value for the whole run
-  }
-  double up_last = 1.0;
-  const int end_lane = (M - 1) / R;
-  const int end_r = (M - 1) - end_lane * R;
-
-  float dyA[DP], dyB[DP], dyC[DP];
-  load_row<DP>(yp, dyA);
-  load_row<DP>(yp + DP, dyB);
-  // a multiple of 3 steps; the extra steps are inactive for every lane
-  const int32_t nsteps = ((total32 + 63 + 2) / 3) * 3;
-
-  // Three y-row buffers: step t reads buffer t % 3 and refills buffer
-  // (t + 2) % 3, which step t - 1 has finished with, so the two-step-ahead
-  // load never overlaps a live row wherever the compiler places it.
-  auto step = [&](float (&dy)[DP], float (&refill)[DP]) {
-    load_row<DP>(yp + 2 * DP, refill);
-    float h32[CR];
-#pragma unroll
-    for (int c = 0; c < CR; ++c) {
-      float s = 0.0f;
-#pragma unroll
-      for (int k = 0; k < D; ++k) s = __builtin_fmaf(dx[c][k], dy[k], s);
-      h32[c] = s;
-    }
-
-#pragma unroll
-    for (int cc = 0; cc < S; ++cc) up[cc] = from_prev_lane(pub[cc], up[cc]);
-
-    if ((uint32_t)g < (uint32_t)total32) {
-      double gk[CR];
-#pragma unroll
-      for (int c = 0; c < CR; ++c) gk[c] = 1.0 + (double)h32[c];
-      // the R x S block of this step in antidiagonal order: S independent
-      // dependency chains for the scheduler
-      double v[R][S];
-#pragma unroll
-      for (int dgl = 0; dgl < R + S - 1; ++dgl) {
-#pragma unroll
-        for (int cc = 0; cc < S; ++cc) {
-          const int r = dgl - cc;
-          if (r < 0 || r >= R) continue;
-          const double A = (cc == 0) ? u[r] : v[r][cc - 1];
-          const double B = (r == 0) ? up[cc] : v[r - 1][cc];
-          const double C = (r == 0) ? ((cc == 0) ? up_last : up[cc - 1])
-                                    : ((cc == 0) ? u[r - 1] : v[r - 1][cc - 1]);
-          v[r][cc] = __builtin_fma(gk[(R >= S) ? (r >> LAM) : 0], A + B, -C);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r) u[r] = v[r][S - 1];
-#pragma unroll
-      for (int cc = 0; cc < S; ++cc) pub[cc] = v[R - 1][cc];
-      up_last = up[S - 1];
-      if (++q == cn) {
-        // last column of a pair: emit its terminal value, then the left
-        // boundary (value 1) of the next pair of the run
-        if (lane == end_lane) {
-          double fv = 1.0;
-#pragma unroll
-          for (int r = 0; r < R; ++r)
-            if (r == end_r) fv = u[r];
-          const int64_t cb = b0 + g / cn;
-          store_out(a, ia, cb, (a.mode == 2 && a.no_diag && cb == ia) ? 0.0f : (float)fv);
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) u[r] = 1.0;
-        up_last = 1.0;
-        q = 0;
-      }
-    }
-    ++g;
-    yp += DP;
-  };
-
-  for (int32_t t = 0; t < nsteps; t += 3) {
-    step(dyA, dyC);
-    step(dyB, dyA);
-    step(dyC, dyB);
-  }
-}
-
-using SweepFn = void (*)(const SweepArgs);
-
-// Register budget: dx (CR x D floats) and the row state (R doubles).
-constexpr bool fits(int R, int LAM, int D) {
-  return ((R >> LAM) > 0 ? (R >> LAM) : 1) * D <= 96 && R <= 32;
-}
-
-template <int R, int LAM, int D>
-SweepFn pick_d() {
-  if constexpr (fits(R, LAM, D))
-    return &sweep_kernel<R, LAM, D>;
-  else
-    return nullptr;
-}
-
-template <int R, int LAM>
-SweepFn pick_lam(int d) {
-  switch (d) {
-    case 1: return pick_d<R, LAM, 1>();
-    case 2: return pick_d<R, LAM, 2>();
-    case 3: return pick_d<R, LAM, 3>();
-    case 4: return pick_d<R, LAM, 4>();
-    case 5: return pick_d<R, LAM, 5>();
-    case 6: return pick_d<R, LAM, 6>();
-    case 7: return pick_d<R, LAM, 7>();
-    case 8: return pick_d<R, LAM, 8>();
-    case 9: return pick_d<R, LAM, 9>();
-    case 10: return pick_d<R, LAM, 10>();
-    case 11: return pick_d<R, LAM, 11>();
-    case 12: return pick_d<R, LAM, 12>();
-    case 13: return pick_d<R, LAM, 13>();
-    case 14: return pick_d<R, LAM, 14>();
-    case 15: return pick_d<R, LAM, 15>();
-    case 16: return pick_d<R, LAM, 16>();
-    default: return nullptr;
-  }
-}
-
-template <int R>
-SweepFn pick_r(int lam, int d) {
-  switch (lam) {
-    case 0: return pick_lam<R, 0>(d);
-    case 1: return pick_lam<R, 1>(d);
-    case 2: return pick_lam<R, 2>(d);
-    case 3: return pick_lam<R, 3>(d);
-    default: return nullptr;
-  }
-}
-
-SweepFn pick(int R, int lam, int d) {
-  switch (R) {
-    case 1: return pick_r<1>(lam, d);
-    case 2: return pick_r<2>(lam, d);
-    case 4: return pick_r<4>(lam, d);
-    case 8: return pick_r<8>(lam, d);
-    case 16: return pick_r<16>(lam, d);
-    case 32: return pick_r<32>(lam, d);
-    default: return nullptr;
-  }
-}
+};
 
 }  // namespace
 
 int choose_rows_per_lane(int64_t fine_rows, int lam, int d) {
   for (int R = 1; R <= kMaxRowsPerLane; R *= 2) {
     if (64 * (int64_t)R < fine_rows) continue;
-    return pick(R, lam, d) ? R : 0;
+    return pick<FwdPlain>(R, lam, d) ? R : 0;
   }
   return 0;
 }
 
 hipError_t launch_sweep(const SweepArgs& a, int lam, int R, int d, hipStream_t stream) {
-  SweepFn f = pick(R, lam, d);
+  FwdPlain::Fn f = pick<FwdPlain>(R, lam, d);
   if (!f) return hipErrorInvalidValue;
   if (a.n_waves == 0) return hipSuccess;
   constexpr int kWavesPerBlock = 4;

@@ -1,0 +1,136 @@
+"""GPU gradients of the Gram (C ABI sigkernel_gram_backward and the autograd
+wrappers) against the FP64 oracle's discrete adjoint on the same float32
+inputs.  The oracle's adjoint is itself pinned by central finite differences
+of the oracle forward (tests/test_oracle_pins.py).
+
+Tolerance: |g_gpu - g_ref| <= 2e-5 max|g_ref| per gradient tensor (the GPU
+forms increments, their inner products and the increment-gradient
+contractions in float32; the sweep and its adjoint run in double).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2006_14794_amd as sk
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 2e-5
+
+
+def cuda(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).cuda()
+
+
+def close(got, ref, rtol=RTOL):
+    got = np.asarray(got, dtype=np.float64)
+    scale = max(np.abs(ref).max(), 1e-30)
+    err = np.abs(got - ref).max() / scale
+    assert err <= rtol, err
+    return err
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sk.load()
+
+
+@pytest.mark.parametrize("lam", [0, 1, 2, 3])
+@pytest.mark.parametrize("d", [1, 4, 9])
+def test_gram_backward_matches_oracle_adjoint(lam, d):
+    X, Y = workloads.gram_batch(seed=800 + d, n_x=3, n_y=4, n_points=23, dim=d - 1)
+    rng = np.random.default_rng(lam)
+    dK = rng.normal(size=(3, 4)).astype(np.float32)
+    gx, gy = sk.sigkernel_gram_backward(cuda(X), cuda(Y), cuda(dK), lam)
+    rx, ry = oracle.gram_backward(X.astype(np.float64), Y.astype(np.float64),
+                                  dK.astype(np.float64), lam)
+    close(gx.cpu().numpy(), rx)
+    close(gy.cpu().numpy(), ry)
+
+
+@pytest.mark.parametrize("run", [1, 2, 3, 7])
+def test_gram_backward_streamed_runs(run, monkeypatch):
+    monkeypatch.setenv("SIGKERNEL_GRAM_RUN", str(run))
+    X, Y = workloads.gram_batch(seed=901, n_x=2, n_y=7, n_points=40, dim=4)
+    dK = np.random.default_rng(2).normal(size=(2, 7)).astype(np.float32)
+    gx, gy = sk.sigkernel_gram_backward(cuda(X), cuda(Y), cuda(dK), 1)
+    rx, ry = oracle.gram_backward(X.astype(np.float64), Y.astype(np.float64),
+                                  dK.astype(np.float64), 1)
+    close(gx.cpu().numpy(), rx)
+    close(gy.cpu().numpy(), ry)
+
+
+@pytest.mark.parametrize("no_diag", [False, True])
+@pytest.mark.parametrize("run", [1, 3])
+def test_symmetric_gram_backward(no_diag, run, monkeypatch):
+    monkeypatch.setenv("SIGKERNEL_GRAM_RUN", str(run))
+    X, _ = workloads.gram_batch(seed=902, n_x=5, n_y=1, n_points=30, dim=3)
+    dK = np.random.default_rng(3).normal(size=(5, 5)).astype(np.float32)
+    gx, gy = sk.sigkernel_gram_backward(cuda(X), None, cuda(dK), 2, symmetric=True,
+                                        no_diag=no_diag)
+    assert gy is None
+    w = dK.astype(np.float64).copy()
+    if no_diag:
+        np.fill_diagonal(w, 0.0)
+    rx, ry = oracle.gram_backward(X.astype(np.float64), X.astype(np.float64), w, 2)
+    close(gx.cpu().numpy(), rx + ry)
+
+
+def test_autograd_gram_and_symmetric():
+    X, Y = workloads.gram_batch(seed=903, n_x=4, n_y=3, n_points=33, dim=2)
+    Xt = cuda(X).requires_grad_(True)
+    Yt = cuda(Y).requires_grad_(True)
+    W = torch.tensor(np.random.default_rng(4).normal(size=(4, 3)), dtype=torch.float32,
+                     device="cuda")
+    loss = (sk.gram(Xt, Yt, 1) * W).sum()
+    loss.backward()
+    rx, ry = oracle.gram_backward(X.astype(np.float64), Y.astype(np.float64),
+                                  W.cpu().numpy().astype(np.float64), 1)
+    close(Xt.grad.cpu().numpy(), rx)
+    close(Yt.grad.cpu().numpy(), ry)
+    # symmetric, unbiased (zero diagonal)
+    Xs = cuda(X).requires_grad_(True)
+    Ks = sk.gram(Xs, None, 1, no_diag=True)
+    assert torch.all(torch.diagonal(Ks) == 0)
+    Ws = torch.ones((4, 4), device="cuda")
+    (Ks * Ws).sum().backward()
+    w = np.ones((4, 4))
+    np.fill_diagonal(w, 0.0)
+    rx, ry = oracle.gram_backward(X.astype(np.float64), X.astype(np.float64), w, 1)
+    close(Xs.grad.cpu().numpy(), rx + ry)
+
+
+def test_one_point_paths_have_zero_gradient():
+    X = torch.ones((2, 1, 3), device="cuda")
+    Y = cuda(workloads.random_paths(5, 3, 6, 3))
+    gx, gy = sk.sigkernel_gram_backward(X, Y, torch.ones((2, 3), device="cuda"), 1)
+    assert torch.all(gx == 0) and torch.all(gy == 0)
+
+
+def test_translation_invariance_of_gpu_gradient():
+    # k depends on increments only: gradients sum to zero over the points of a path
+    X, Y = workloads.gram_batch(seed=904, n_x=2, n_y=2, n_points=50, dim=4)
+    dK = torch.ones((2, 2), device="cuda")
+    gx, gy = sk.sigkernel_gram_backward(cuda(X), cuda(Y), dK, 1)
+    s = gx.sum(dim=1).abs().max().item()
+    assert s <= 1e-5 * gx.abs().max().item()
+
+
+def test_mmd_workload_full_size_sampled_pairs():
+    # 64 generated paths vs 64 OU targets, 512 points, d = 4, dyadic order 1:
+    # the launch configuration of the MMD workload, with a sparse upstream
+    # weight so that the oracle only solves the pairs it touches
+    X, Y = workloads.mmd_paths()
+    rng = np.random.default_rng(5)
+    dK = np.zeros((64, 64), dtype=np.float32)
+    for _ in range(6):
+        dK[rng.integers(64), rng.integers(64)] = rng.normal()
+    gx, gy = sk.sigkernel_gram_backward(cuda(X), cuda(Y), cuda(dK), 1)
+    rx, ry = oracle.gram_backward(X.astype(np.float64), Y.astype(np.float64),
+                                  dK.astype(np.float64), 1)
+    close(gx.cpu().numpy(), rx)
+    close(gy.cpu().numpy(), ry)
