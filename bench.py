@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-pairs", type=int, default=0,
                     help="pairs of the workload timed on the CPU oracle (0: auto)")
+    ap.add_argument("--workload", choices=["gram", "mmd"], default="gram",
+                    help="gram: the 128 x 128 Gram batch (default, the reported metric); "
+                         "mmd: unbiased MMD^2 of 64 vs 64 512-point paths with its gradient")
     return ap.parse_args()
 
 
@@ -74,12 +77,72 @@ def cpu_baseline(X, Y, lam, n_sample, K_gpu):
             "gpu_max_err_on_sample": float(err.max())}
 
 
+def time_steps(fn, steps, warmup):
+    """Run fn warmup + steps times; per-step HIP-event durations and the wall
+    time of the timed steps, synchronised on both sides."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record(stream)
+        fn()
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [s.elapsed_time(e) for s, e in zip(starts, ends)], wall
+
+
+def bench_mmd(args):
+    """Unbiased MMD^2 between 64 generated paths (the parameters) and 64 OU
+    targets, 512 points in R^4, dyadic order 1: value and gradient in X."""
+    import torch
+    import paper_2006_14794_amd as sk
+    import workloads
+    lam = 1
+    X, Y = workloads.mmd_paths()
+    n, L, d = X.shape
+    m = Y.shape[0]
+    dev = torch.device("cuda:0")
+    Xt, Yt = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
+    ws = torch.empty(sk.workspace_bytes(3, Xt, Yt, lam, 4), dtype=torch.uint8, device=dev)
+
+    def step():
+        sk.sigkernel_mmd2(Xt, Yt, lam, grad=True, workspace=ws)
+
+    per, wall = time_steps(step, args.steps, args.warmup)
+    ms = wall * 1e3 / args.steps
+    cells = ((L - 1) << lam) ** 2
+    fwd_pairs = n * (n - 1) // 2 + m * (m - 1) // 2 + n * m
+    bwd_pairs = n * (n - 1) // 2 + n * m
+    work = (fwd_pairs + bwd_pairs) * cells
+    rec = {
+        "metric": "Goursat grid-cell updates/s, MMD^2 forward + adjoint",
+        "value": work / (ms / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "unbiased MMD^2, 64 random walks vs 64 OU paths, 512 points, "
+                               "d=4, dyadic order 1, value + gradient in X",
+                   "forward_pairs": fwd_pairs, "adjoint_pairs": bwd_pairs,
+                   "fine_cells_per_pair": cells},
+        "avg_event_ms": float(np.mean(per)),
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "mmd":
+        bench_mmd(args)
+        return
 
     import torch
     import paper_2006_14794_amd as sk

@@ -79,7 +79,8 @@ typedef struct sk_paths {
 /* flags */
 enum {
     SK_SYMMETRIC = 1u << 0,   /* gram only: X and Y are the same batch; solve a <= b and mirror */
-    SK_NO_DIAG   = 1u << 1    /* gram only, with SK_SYMMETRIC: write 0 on the diagonal         */
+    SK_NO_DIAG   = 1u << 1,   /* gram only, with SK_SYMMETRIC: write 0 on the diagonal         */
+    SK_MMD2_GRAD = 1u << 2    /* mmd2 only: also write the gradient with respect to X          */
 };
 
 /*
@@ -127,8 +128,23 @@ sk_status sigkernel_gram_backward(const sk_paths *X, const sk_paths *Y, int32_t 
                                   uint32_t flags, const float *dK, float *dX, float *dY,
                                   void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * sigkernel_mmd2 -- unbiased MMD^2 between the laws of two batches of paths
+ * under the signature kernel (the unbiased estimator mentioned at the end of
+ * Section 3.1.1, used there to train generative models of paths):
+ *   MMD^2 = sum_{a != b} k(X_a, X_b) / (n (n - 1)) + sum_{a != b} k(Y_a, Y_b) / (m (m - 1))
+ *           - 2 sum_{a, b} k(X_a, Y_b) / (n m),     n, m >= 2,
+ * with k the explicit scheme on P_lambda.  mmd2: DEVICE float[1].  With
+ * SK_MMD2_GRAD, dX (DEVICE, shaped like X's points) receives d MMD^2 / d X;
+ * Y is treated as fixed data.  Uniform batches only.  Workspace:
+ * sigkernel_workspace_bytes(SK_OP_MMD2, X, Y, dyadic_order, flags).
+ */
+sk_status sigkernel_mmd2(const sk_paths *X, const sk_paths *Y, int32_t dyadic_order,
+                         uint32_t flags, float *mmd2, float *dX, void *ws, size_t ws_bytes,
+                         void *stream);
+
 /* Workspace sizing.  op is one of the SK_OP_* values. */
-enum { SK_OP_PAIR = 0, SK_OP_GRAM = 1, SK_OP_GRAM_BACKWARD = 2 };
+enum { SK_OP_PAIR = 0, SK_OP_GRAM = 1, SK_OP_GRAM_BACKWARD = 2, SK_OP_MMD2 = 3 };
 size_t sigkernel_workspace_bytes(int32_t op, const sk_paths *X, const sk_paths *Y,
                                  int32_t dyadic_order, uint32_t flags);
 

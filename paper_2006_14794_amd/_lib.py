@@ -24,16 +24,19 @@ SK_ERR_UNSUPPORTED = -7
 
 SK_SYMMETRIC = 1 << 0
 SK_NO_DIAG = 1 << 1
+SK_MMD2_GRAD = 1 << 2
 
 SK_OP_PAIR = 0
 SK_OP_GRAM = 1
 SK_OP_GRAM_BACKWARD = 2
+SK_OP_MMD2 = 3
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTED = (
     "sigkernel_pair",
     "sigkernel_gram",
     "sigkernel_gram_backward",
+    "sigkernel_mmd2",
     "sigkernel_workspace_bytes",
     "sigkernel_status_string",
     "sigkernel_version",
@@ -78,6 +81,8 @@ def load():
     lib.sigkernel_gram.restype = i32
     lib.sigkernel_gram_backward.argtypes = [P, P, i32, u32, vp, vp, vp, vp, sz, vp]
     lib.sigkernel_gram_backward.restype = i32
+    lib.sigkernel_mmd2.argtypes = [P, P, i32, u32, vp, vp, vp, sz, vp]
+    lib.sigkernel_mmd2.restype = i32
     lib.sigkernel_workspace_bytes.argtypes = [i32, P, P, i32, u32]
     lib.sigkernel_workspace_bytes.restype = sz
     lib.sigkernel_status_string.argtypes = [i32]

@@ -231,3 +231,43 @@ def gram(X: torch.Tensor, Y: Optional[torch.Tensor] = None, dyadic_order: int = 
     if Y is None:
         return SigKernelGramSymmetric.apply(X, dyadic_order, no_diag)
     return SigKernelGram.apply(X, Y, dyadic_order)
+
+
+def sigkernel_mmd2(X: torch.Tensor, Y: torch.Tensor, dyadic_order: int = 0, *,
+                   grad: bool = False, workspace: Optional[torch.Tensor] = None):
+    """(mmd2 [1] device tensor, dX or None): unbiased MMD^2 between the batches
+    and, with ``grad=True``, its gradient with respect to the points of X."""
+    lib = _lib.load()
+    dev = _device(X)
+    flags = _lib.SK_MMD2_GRAD if grad else 0
+    sx, sy = _describe(X), _describe(Y)
+    out = torch.empty(1, dtype=torch.float32, device=dev)
+    dX = torch.empty_like(X) if grad else None
+    nbytes = int(lib.sigkernel_workspace_bytes(_lib.SK_OP_MMD2, ctypes.byref(sx),
+                                               ctypes.byref(sy), int(dyadic_order), flags))
+    ws = _workspace(nbytes, dev, workspace)
+    st = lib.sigkernel_mmd2(ctypes.byref(sx), ctypes.byref(sy), int(dyadic_order), flags,
+                            out.data_ptr(), dX.data_ptr() if dX is not None else None,
+                            ws.data_ptr(), ws.numel() * ws.element_size(), _stream_ptr(dev))
+    _lib.check(st, "sigkernel_mmd2")
+    return out, dX
+
+
+class SigKernelMMD2(torch.autograd.Function):
+    """Unbiased MMD^2 with its gradient computed in the same library call."""
+
+    @staticmethod
+    def forward(ctx, X, Y, dyadic_order):
+        val, dX = sigkernel_mmd2(X, Y, dyadic_order, grad=ctx.needs_input_grad[0])
+        ctx.save_for_backward(dX if dX is not None else torch.empty(0, device=X.device))
+        return val[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (dX,) = ctx.saved_tensors
+        return (dX * g) if dX.numel() else None, None, None
+
+
+def mmd2(X: torch.Tensor, Y: torch.Tensor, dyadic_order: int = 0) -> torch.Tensor:
+    """Differentiable (in X) unbiased signature-kernel MMD^2."""
+    return SigKernelMMD2.apply(X, Y, dyadic_order)

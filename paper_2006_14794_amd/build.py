@@ -38,7 +38,8 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 8, verbose: bool = True) -> str:
+def build(jobs: int = 0, verbose: bool = True) -> str:
+    jobs = jobs or min(16, os.cpu_count() or 8)
     os.makedirs(BUILD_DIR, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

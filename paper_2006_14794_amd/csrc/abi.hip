@@ -185,6 +185,45 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_
   return e == hipSuccess ? SK_OK : SK_ERR_HIP;
 }
 
+// MMD^2 workspace: the three Gram blocks, the two upstream weight matrices,
+// a temporary gradient, then the largest workspace of the calls it makes
+// (they run one after the other on the stream and share it).
+struct Mmd2Layout {
+  size_t kxx, kyy, kxy, wxx, wxy, tmp, sub, sub_bytes, total;
+};
+
+Mmd2Layout mmd2_layout(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t flags) {
+  const size_t n = (size_t)X->n_paths, m = (size_t)Y->n_paths;
+  Mmd2Layout L{};
+  size_t off = 0;
+  L.kxx = off;
+  off += align256(n * n * sizeof(float));
+  L.kyy = off;
+  off += align256(m * m * sizeof(float));
+  L.kxy = off;
+  off += align256(n * m * sizeof(float));
+  L.wxx = off;
+  off += align256(n * n * sizeof(float));
+  L.wxy = off;
+  off += align256(n * m * sizeof(float));
+  L.tmp = off;
+  off += align256((size_t)X->n_paths * X->len * X->dim * sizeof(float));
+  size_t sub = forward_ws(X, X);
+  const size_t c[] = {forward_ws(Y, Y), forward_ws(X, Y)};
+  for (size_t v : c) sub = v > sub ? v : sub;
+  if (flags & SK_MMD2_GRAD) {
+    const size_t b1 = backward_plan(X, X, lam, SK_SYMMETRIC | SK_NO_DIAG).total;
+    const size_t b2 = backward_plan(X, Y, lam, 0).total;
+    sub = b1 > sub ? b1 : sub;
+    sub = b2 > sub ? b2 : sub;
+  }
+  L.sub = off;
+  L.sub_bytes = sub;
+  off += align256(sub);
+  L.total = off;
+  return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -217,6 +256,9 @@ size_t sigkernel_workspace_bytes(int32_t op, const sk_paths* X, const sk_paths* 
     case SK_OP_GRAM_BACKWARD:
       if (X->offsets || Y->offsets || X->dim != Y->dim) return 0;
       return backward_plan(X, Y, dyadic_order, flags).total;
+    case SK_OP_MMD2:
+      if (X->offsets || Y->offsets || X->dim != Y->dim) return 0;
+      return mmd2_layout(X, Y, dyadic_order, flags).total;
     default:
       return 0;
   }
@@ -254,6 +296,57 @@ sk_status sigkernel_gram(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
   if (!ws) return SK_ERR_WORKSPACE;
   return run_forward(X, Y, dyadic_order, flags, K, ws, ws_bytes,
                      static_cast<hipStream_t>(stream), (flags & SK_SYMMETRIC) ? 2 : 1);
+}
+
+sk_status sigkernel_mmd2(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
+                         uint32_t flags, float* mmd2, float* dX, void* ws, size_t ws_bytes,
+                         void* stream) {
+  if (!X || !Y || !mmd2) return SK_ERR_NULL;
+  if (!valid_batch(X) || !valid_batch(Y)) return SK_ERR_SHAPE;
+  if (X->dim != Y->dim || X->n_paths < 2 || Y->n_paths < 2) return SK_ERR_SHAPE;
+  if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (sk_status f = check_flags(flags, SK_MMD2_GRAD)) return f;
+  if ((flags & SK_MMD2_GRAD) && !dX) return SK_ERR_NULL;
+  if (X->offsets || Y->offsets) return SK_ERR_UNSUPPORTED;
+  if (!X->points || !Y->points) return SK_ERR_NULL;
+  if (!ws) return SK_ERR_WORKSPACE;
+  const Mmd2Layout L = mmd2_layout(X, Y, dyadic_order, flags);
+  if (ws_bytes < L.total) return SK_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  float* kxx = reinterpret_cast<float*>(base + L.kxx);
+  float* kyy = reinterpret_cast<float*>(base + L.kyy);
+  float* kxy = reinterpret_cast<float*>(base + L.kxy);
+  void* sub = base + L.sub;
+  const uint32_t unb = SK_SYMMETRIC | SK_NO_DIAG;
+  sk_status r;
+  if ((r = sigkernel_gram(X, X, dyadic_order, unb, kxx, sub, L.sub_bytes, stream))) return r;
+  if ((r = sigkernel_gram(Y, Y, dyadic_order, unb, kyy, sub, L.sub_bytes, stream))) return r;
+  if ((r = sigkernel_gram(X, Y, dyadic_order, 0, kxy, sub, L.sub_bytes, stream))) return r;
+  if (sk::launch_mmd2_reduce(kxx, X->n_paths, kyy, Y->n_paths, kxy, mmd2, st) != hipSuccess)
+    return SK_ERR_HIP;
+  if (flags & SK_MMD2_GRAD) {
+    const int64_t n = X->n_paths, m = Y->n_paths;
+    float* wxx = reinterpret_cast<float*>(base + L.wxx);
+    float* wxy = reinterpret_cast<float*>(base + L.wxy);
+    float* tmp = reinterpret_cast<float*>(base + L.tmp);
+    // d MMD^2 / d Kxx[a][b] = 1 / (n (n - 1)) off the diagonal (the symmetric
+    // backward ignores the diagonal); d MMD^2 / d Kxy[a][b] = -2 / (n m)
+    if (sk::launch_fill(wxx, n * n, (float)(1.0 / ((double)n * (double)(n - 1))), st) !=
+        hipSuccess)
+      return SK_ERR_HIP;
+    if (sk::launch_fill(wxy, n * m, (float)(-2.0 / ((double)n * (double)m)), st) != hipSuccess)
+      return SK_ERR_HIP;
+    if ((r = sigkernel_gram_backward(X, X, dyadic_order, unb, wxx, dX, nullptr, sub, L.sub_bytes,
+                                     stream)))
+      return r;
+    if ((r = sigkernel_gram_backward(X, Y, dyadic_order, 0, wxy, tmp, nullptr, sub, L.sub_bytes,
+                                     stream)))
+      return r;
+    if (sk::launch_add(dX, tmp, X->n_paths * X->len * X->dim, st) != hipSuccess)
+      return SK_ERR_HIP;
+  }
+  return SK_OK;
 }
 
 sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,

@@ -12,6 +12,12 @@ constexpr bool sweep_fits(int R, int LAM, int D) {
   return ((R >> LAM) > 0 ? (R >> LAM) : 1) * D <= 96 && R <= 32;
 }
 
+// The adjoint keeps a second x-increment row, the gradient accumulators and
+// the stored cell sums in registers as well: a tighter budget (no spills).
+constexpr bool adjoint_fits(int R, int LAM, int D) {
+  return ((R >> LAM) > 0 ? (R >> LAM) : 1) * D <= 72 && R <= 16;
+}
+
 template <class F, int R, int LAM>
 typename F::Fn pick_d(int d) {
   switch (d) {

@@ -109,6 +109,15 @@ hipError_t launch_point_grad(const float* part_x, int64_t runs_per_row, float sc
                              bool col_upper, int64_t n_paths, int32_t len, int32_t d, float* out,
                              hipStream_t stream);
 
+hipError_t launch_mmd2_reduce(const float* kxx, int64_t n, const float* kyy, int64_t m,
+                              const float* kxy, float* out, hipStream_t stream);
+hipError_t launch_add(float* dst, const float* src, int64_t n, hipStream_t stream);
+
+// Compiled sweep kernels by kind, dyadic order, rows per lane and channels
+// (nullptr when the configuration is not compiled).
+enum { kKernelForward = 0, kKernelForwardStore = 1, kKernelAdjoint = 2 };
+void* sweep_fn(int kind, int lam, int rows_per_lane, int dim);
+
 // Steps of a wave that streams `total` coarse columns (a multiple of three:
 // the y-row prefetch rotates three buffers).
 __host__ __device__ inline int64_t sweep_steps(int64_t total) {

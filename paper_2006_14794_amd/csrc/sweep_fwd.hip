@@ -1,39 +1,52 @@
-// Forward sweep launches (value only).  Kernel: sweep_fwd_kernel.h.
-#include "dispatch.h"
-#include "sweep_fwd_kernel.h"
+// Launchers of the forward sweep kernels (sweep_fwd_kernel.h) and the table of
+// compiled configurations (instantiated per dyadic order in sweep_lam*.hip).
+#include "internal.h"
 
 namespace sk {
-namespace {
 
-struct FwdPlain {
-  using Fn = void (*)(const SweepArgs);
-  template <int R, int LAM, int D>
-  static Fn get() {
-    if constexpr (sweep_fits(R, LAM, D))
-      return &fwd::sweep_kernel<R, LAM, D, false>;
-    else
-      return nullptr;
-  }
-};
+#define SK_DECL(k, l) void* sweep_fn_k##k##_l##l##_(int R, int d);
+SK_DECL(0, 0) SK_DECL(0, 1) SK_DECL(0, 2) SK_DECL(0, 3)
+SK_DECL(1, 0) SK_DECL(1, 1) SK_DECL(1, 2) SK_DECL(1, 3)
+SK_DECL(2, 0) SK_DECL(2, 1) SK_DECL(2, 2) SK_DECL(2, 3)
+#undef SK_DECL
 
-}  // namespace
+void* sweep_fn(int kind, int lam, int R, int d) {
+  using Pick = void* (*)(int, int);
+  static const Pick table[3][4] = {
+      {sweep_fn_k0_l0_, sweep_fn_k0_l1_, sweep_fn_k0_l2_, sweep_fn_k0_l3_},
+      {sweep_fn_k1_l0_, sweep_fn_k1_l1_, sweep_fn_k1_l2_, sweep_fn_k1_l3_},
+      {sweep_fn_k2_l0_, sweep_fn_k2_l1_, sweep_fn_k2_l2_, sweep_fn_k2_l3_}};
+  if (kind < 0 || kind > 2 || lam < 0 || lam > 3) return nullptr;
+  return table[kind][lam](R, d);
+}
 
 int choose_rows_per_lane(int64_t fine_rows, int lam, int d) {
   for (int R = 1; R <= kMaxRowsPerLane; R *= 2) {
     if (64 * (int64_t)R < fine_rows) continue;
-    return pick<FwdPlain>(R, lam, d) ? R : 0;
+    return sweep_fn(kKernelForward, lam, R, d) ? R : 0;
   }
   return 0;
 }
 
-hipError_t launch_sweep(const SweepArgs& a, int lam, int R, int d, hipStream_t stream) {
-  FwdPlain::Fn f = pick<FwdPlain>(R, lam, d);
+namespace {
+hipError_t launch_forward(int kind, const SweepArgs& a, int lam, int R, int d,
+                          hipStream_t stream) {
+  auto f = reinterpret_cast<void (*)(const SweepArgs)>(sweep_fn(kind, lam, R, d));
   if (!f) return hipErrorInvalidValue;
   if (a.n_waves == 0) return hipSuccess;
   constexpr int kWavesPerBlock = 4;
   const int64_t blocks = (a.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
   hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, stream, a);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_sweep(const SweepArgs& a, int lam, int R, int d, hipStream_t stream) {
+  return launch_forward(kKernelForward, a, lam, R, d, stream);
+}
+
+hipError_t launch_sweep_store(const SweepArgs& a, int lam, int R, int d, hipStream_t stream) {
+  return launch_forward(kKernelForwardStore, a, lam, R, d, stream);
 }
 
 }  // namespace sk

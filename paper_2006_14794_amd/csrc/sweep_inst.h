@@ -1,0 +1,75 @@
+// Instantiations of one sweep kernel (SK_KIND: forward, forward with store,
+// adjoint) at one dyadic order SK_LAM.  Included by sweep_k{kind}_l{lam}.hip
+// so that the configurations compile in parallel translation units.
+#include "dispatch.h"
+#if SK_KIND == 2
+#include "sweep_bwd_kernel.h"
+#else
+#include "sweep_fwd_kernel.h"
+#endif
+
+#define SK_CAT2(a, b) a##b
+#define SK_CAT(a, b) SK_CAT2(a, b)
+
+namespace sk {
+namespace {
+
+#if SK_KIND == 0
+struct FwdPlain {
+  using Fn = void*;
+  template <int R, int LAM, int D>
+  static Fn get() {
+    if constexpr (sweep_fits(R, LAM, D))
+      return reinterpret_cast<void*>(&fwd::sweep_kernel<R, LAM, D, false>);
+    else
+      return nullptr;
+  }
+};
+#elif SK_KIND == 1
+struct FwdStore {
+  using Fn = void*;
+  template <int R, int LAM, int D>
+  static Fn get() {
+    if constexpr (sweep_fits(R, LAM, D))
+      return reinterpret_cast<void*>(&fwd::sweep_kernel<R, LAM, D, true>);
+    else
+      return nullptr;
+  }
+};
+#else
+struct Adjoint {
+  using Fn = void*;
+  template <int R, int LAM, int D>
+  static Fn get() {
+    if constexpr (sweep_fits(R, LAM, D) && adjoint_fits(R, LAM, D))
+      return reinterpret_cast<void*>(&bwd::adjoint_kernel<R, LAM, D>);
+    else
+      return nullptr;
+  }
+};
+#endif
+
+template <class F>
+void* pick_fixed_lam(int R, int d) {
+  switch (R) {
+    case 1: return pick_d<F, 1, SK_LAM>(d);
+    case 2: return pick_d<F, 2, SK_LAM>(d);
+    case 4: return pick_d<F, 4, SK_LAM>(d);
+    case 8: return pick_d<F, 8, SK_LAM>(d);
+    case 16: return pick_d<F, 16, SK_LAM>(d);
+    case 32: return pick_d<F, 32, SK_LAM>(d);
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+#if SK_KIND == 0
+void* SK_CAT(SK_CAT(sweep_fn_k0_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<FwdPlain>(R, d); }
+#elif SK_KIND == 1
+void* SK_CAT(SK_CAT(sweep_fn_k1_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<FwdStore>(R, d); }
+#else
+void* SK_CAT(SK_CAT(sweep_fn_k2_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Adjoint>(R, d); }
+#endif
+
+}  // namespace sk
