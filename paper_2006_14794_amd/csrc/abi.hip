@@ -1,6 +1,7 @@
 // C ABI of libsigkernel: argument validation, workspace layout, launches.
 // Declarations and contracts: include/sigkernel.h.
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -82,6 +83,47 @@ int64_t choose_run(int64_t nx, int64_t ny) {
   return run;
 }
 
+// Independent pairs: the forward layout (increments not scaled), the pair
+// plan (order, class counts, queue counters) and one band buffer per
+// persistent wave slot.
+constexpr int64_t kPairSlots = 4096;
+
+struct PairLayout {
+  int rows_lo, rows_hi;
+  int64_t slots, band_stride;  // doubles per slot
+  size_t order, counts, bands, total;
+};
+
+PairLayout pair_layout(const sk_paths* X, const sk_paths* Y, int32_t lam, bool gram) {
+  PairLayout L{};
+  const int64_t npairs = gram ? X->n_paths * Y->n_paths : X->n_paths;
+  const int d = X->dim;
+  // rows of the longest possible pair (its shorter path on the rows)
+  const int64_t shorter = (X->len < Y->len ? X->len : Y->len) - 1;
+  const int64_t rows = (shorter < 1 ? 1 : shorter) << lam;
+  int rmax = 0;
+  for (int R = 1; R <= sk::kMaxRowsPerLane; R *= 2)
+    if (sk::sweep_fn(sk::kKernelPair, lam, R, d)) rmax = R;
+  int rhi = 1;
+  while (rhi < rmax && 64 * (int64_t)rhi < rows) rhi *= 2;
+  L.rows_hi = rmax ? rhi : 0;
+  L.rows_lo = rhi > 1 ? rhi / 2 : rhi;
+  // wave slots: a whole number of 4-wave workgroups
+  L.slots = npairs < kPairSlots ? npairs : kPairSlots;
+  L.slots = ((L.slots < 1 ? 1 : L.slots) + 3) & ~int64_t(3);
+  const int64_t longer = (X->len > Y->len ? X->len : Y->len);
+  L.band_stride = (longer + 2 * sk::kStreamPad) << lam;
+  size_t off = forward_ws(X, Y);
+  L.order = off;
+  off += align256((size_t)(npairs > 0 ? npairs : 1) * sizeof(int32_t));
+  L.counts = off;
+  off += 256;  // counts[2], counters[2]
+  L.bands = off;
+  off += align256((size_t)L.slots * (size_t)L.band_stride * sizeof(double));
+  L.total = off;
+  return L;
+}
+
 // Backward workspace: the forward layout, then the per-wave store of one
 // chunk of waves, the per-run x-side and per-pair y-side increment gradients.
 constexpr size_t kStoreCapBytes = size_t(4) << 30;
@@ -99,6 +141,10 @@ BackwardPlan backward_plan(const sk_paths* X, const sk_paths* Y, int32_t lam, ui
   const int64_t m = X->len - 1, n = Y->len - 1;
   const int64_t fine_rows = m << lam;
   P.R = sk::choose_rows_per_lane(fine_rows < 1 ? 1 : fine_rows, lam, X->dim);
+  if (P.R == 0) {  // no compiled configuration: the caller reports SK_ERR_UNSUPPORTED
+    P.total = forward_ws(X, Y);
+    return P;
+  }
   P.run = choose_run(X->n_paths, Y->n_paths);
   P.runs_per_row = (Y->n_paths + P.run - 1) / P.run;
   P.n_waves = X->n_paths * P.runs_per_row;
@@ -129,13 +175,97 @@ sk_status check_flags(uint32_t flags, uint32_t allowed) {
   return SK_OK;
 }
 
+// gram: every (a, b) of the two batches, out[a * ny + b]; else pairs (x_k, y_k)
+sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* out, void* ws,
+                    size_t ws_bytes, hipStream_t stream, bool gram) {
+  const int d = X->dim;
+  const int dp = sk::padded_dim(d);
+  const PairLayout PL = pair_layout(X, Y, lam, gram);
+  const int64_t npairs = gram ? X->n_paths * Y->n_paths : X->n_paths;
+  if (npairs > INT32_MAX) return SK_ERR_UNSUPPORTED;
+  if (PL.rows_hi == 0) return SK_ERR_UNSUPPORTED;
+  if (ws_bytes < PL.total) return SK_ERR_WORKSPACE;
+  const ForwardLayout L = forward_layout(X, Y);
+  char* base = static_cast<char*>(ws);
+  float* incx = reinterpret_cast<float*>(base + L.incx) + sk::kStreamPad * dp;
+  float* incy = reinterpret_cast<float*>(base + L.incy) + sk::kStreamPad * dp;
+  sk::PathPlan px{reinterpret_cast<int32_t*>(base + L.planx_n),
+                  reinterpret_cast<int64_t*>(base + L.planx_start)};
+  sk::PathPlan py{reinterpret_cast<int32_t*>(base + L.plany_n),
+                  reinterpret_cast<int64_t*>(base + L.plany_start)};
+  const sk::Batch bx = to_batch(X), by = to_batch(Y);
+  if (X->offsets && sk::launch_plan(bx, px, stream) != hipSuccess) return SK_ERR_HIP;
+  if (Y->offsets && sk::launch_plan(by, py, stream) != hipSuccess) return SK_ERR_HIP;
+  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, 1.0f, dp, incx, stream) != hipSuccess)
+    return SK_ERR_HIP;
+  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream) != hipSuccess)
+    return SK_ERR_HIP;
+  int32_t* order = reinterpret_cast<int32_t*>(base + PL.order);
+  int32_t* counts = reinterpret_cast<int32_t*>(base + PL.counts);
+  sk::PairPlanArgs pp{};
+  pp.x_n = X->offsets ? px.n : nullptr;
+  pp.x_len = X->len;
+  pp.y_n = Y->offsets ? py.n : nullptr;
+  pp.y_len = Y->len;
+  pp.npairs = (int32_t)npairs;
+  pp.gram_ny = gram ? Y->n_paths : 0;
+  pp.lam = lam;
+  pp.rows_lo = PL.rows_lo;
+  pp.rows_hi = PL.rows_hi;
+  pp.order = order;
+  pp.counts = counts;
+  pp.counters = counts + 2;
+  if (sk::launch_pair_plan(pp, stream) != hipSuccess) return SK_ERR_HIP;
+
+  sk::PairArgs a{};
+  a.incx = incx;
+  a.incy = incy;
+  a.x_n = pp.x_n;
+  a.x_start = X->offsets ? px.start : nullptr;
+  a.y_n = pp.y_n;
+  a.y_start = Y->offsets ? py.start : nullptr;
+  a.x_len = X->len;
+  a.y_len = Y->len;
+  a.scale = ldexp(1.0, -(2 * lam + 1));
+  a.bandbuf = reinterpret_cast<double*>(base + PL.bands);
+  a.band_stride = PL.band_stride;
+  a.out = out;
+  a.gram_ny = pp.gram_ny;
+  // long-row class first (it holds the longest pairs), then the short class
+  a.order = order;
+  a.count = counts;
+  a.counter = counts + 2;
+  hipError_t e = sk::launch_pairs(a, lam, PL.rows_hi, d, PL.slots, stream);
+  if (e == hipSuccess) {
+    // the short class follows the long one in `order`; its offset (the long
+    // class's count) is only known on the device, where the kernel reads it
+    a.order = order;
+    a.count = counts + 1;
+    a.counter = counts + 3;
+    a.order_base = counts;  // start of the short class: order[counts[0]]
+    e = sk::launch_pairs(a, lam, PL.rows_lo, d, PL.slots, stream);
+  }
+  if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;
+  return e == hipSuccess ? SK_OK : SK_ERR_HIP;
+}
+
 sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t flags,
                       float* out, void* ws, size_t ws_bytes, hipStream_t stream, int mode) {
+  if (mode == 0) return run_pairs(X, Y, lam, out, ws, ws_bytes, stream, false);
   const int d = X->dim;
   const int dp = sk::padded_dim(d);
   const int64_t fine_rows = (int64_t)(X->len - 1) << lam;
   const int R = sk::choose_rows_per_lane(fine_rows < 1 ? 1 : fine_rows, lam, d);
-  if (R == 0) return SK_ERR_UNSUPPORTED;
+  if (R == 0) {
+    // x paths taller than one wave's strips: every (a, b) through the
+    // persistent pair kernel with row bands (a symmetric Gram is filled in
+    // both halves by solving both)
+    const sk_status st = run_pairs(X, Y, lam, out, ws, ws_bytes, stream, true);
+    if (st == SK_OK && mode == 2 && (flags & SK_NO_DIAG) &&
+        sk::launch_zero_diag(out, X->n_paths, stream) != hipSuccess)
+      return SK_ERR_HIP;
+    return st;
+  }
   const ForwardLayout L = forward_layout(X, Y);
   if (ws_bytes < L.total) return SK_ERR_WORKSPACE;
 
@@ -251,8 +381,14 @@ size_t sigkernel_workspace_bytes(int32_t op, const sk_paths* X, const sk_paths* 
   if (!valid_batch(X) || !valid_batch(Y)) return 0;
   switch (op) {
     case SK_OP_PAIR:
-    case SK_OP_GRAM:
-      return forward_ws(X, Y);
+      if (X->dim != Y->dim) return 0;
+      return pair_layout(X, Y, dyadic_order, false).total;
+    case SK_OP_GRAM: {
+      const size_t f = forward_ws(X, Y);
+      if (X->dim != Y->dim) return f;
+      const size_t g = pair_layout(X, Y, dyadic_order, true).total;
+      return f > g ? f : g;
+    }
     case SK_OP_GRAM_BACKWARD:
       if (X->offsets || Y->offsets || X->dim != Y->dim) return 0;
       return backward_plan(X, Y, dyadic_order, flags).total;

@@ -112,10 +112,48 @@ hipError_t launch_point_grad(const float* part_x, int64_t runs_per_row, float sc
 hipError_t launch_mmd2_reduce(const float* kxx, int64_t n, const float* kyy, int64_t m,
                               const float* kxy, float* out, hipStream_t stream);
 hipError_t launch_add(float* dst, const float* src, int64_t n, hipStream_t stream);
+hipError_t launch_zero_diag(float* k, int64_t n, hipStream_t stream);  // k[i][i] = 0, k is n x n
+
+// Independent pairs, persistent and length-sorted (pair_kernel.h, pairs.hip).
+struct PairArgs {
+  const float* incx;        // dense increments of both batches, not scaled
+  const float* incy;
+  const int32_t* x_n;       // ragged plans (nullptr for a uniform batch)
+  const int64_t* x_start;
+  const int32_t* y_n;
+  const int64_t* y_start;
+  int32_t x_len, y_len;
+  double scale;             // 2^-(2 lam + 1)
+  const int32_t* order;     // pair ids, long class first, each class longest first
+  const int32_t* order_base;  // device: offset of this class in `order` (nullptr: 0)
+  const int32_t* count;     // device: pairs in this class
+  int32_t* counter;         // device queue head (zeroed by the plan kernel)
+  double* bandbuf;          // per wave slot: band_stride doubles
+  int64_t band_stride;
+  float* out;               // out[pid]
+  int64_t gram_ny;          // 0: pair pid is (x_pid, y_pid); else (x_{pid / gram_ny}, y_{pid % gram_ny})
+};
+
+struct PairPlanArgs {
+  const int32_t* x_n;
+  int32_t x_len;
+  const int32_t* y_n;
+  int32_t y_len;
+  int32_t npairs, lam, rows_lo, rows_hi;
+  int64_t gram_ny;          // as in PairArgs
+  int32_t* order;           // [npairs]: long-row class first
+  int32_t* counts;          // [2]: long class, short class
+  int32_t* counters;        // [2]
+};
+
+hipError_t launch_pair_plan(const PairPlanArgs& p, hipStream_t stream);
+// Persistent launch: min(max_waves, resident waves) wavefronts.
+hipError_t launch_pairs(const PairArgs& a, int lam, int rows_per_lane, int dim,
+                        int64_t max_waves, hipStream_t stream);
 
 // Compiled sweep kernels by kind, dyadic order, rows per lane and channels
 // (nullptr when the configuration is not compiled).
-enum { kKernelForward = 0, kKernelForwardStore = 1, kKernelAdjoint = 2 };
+enum { kKernelForward = 0, kKernelForwardStore = 1, kKernelAdjoint = 2, kKernelPair = 3 };
 void* sweep_fn(int kind, int lam, int rows_per_lane, int dim);
 
 // Steps of a wave that streams `total` coarse columns (a multiple of three:

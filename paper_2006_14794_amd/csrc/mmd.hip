@@ -43,7 +43,19 @@ __global__ __launch_bounds__(256) void add_kernel(float* __restrict__ dst,
     dst[i] += src[i];
 }
 
+__global__ __launch_bounds__(256) void zero_diag_kernel(float* __restrict__ k, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) k[i * n + i] = 0.0f;
+}
+
 }  // namespace
+
+hipError_t launch_zero_diag(float* k, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_diag_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                     k, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_mmd2_reduce(const float* kxx, int64_t n, const float* kyy, int64_t m,
                               const float* kxy, float* out, hipStream_t stream) {

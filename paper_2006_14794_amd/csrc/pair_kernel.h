@@ -1,0 +1,173 @@
+// Independent pairs (x_k, y_k) of uneven lengths: the explicit scheme of
+// Section 3.1, eq. (explicit_finite_diff), on P_lambda, one pair at a time per
+// wavefront, with a persistent grid that takes pairs from a length-sorted
+// device queue (longest first).
+//
+// Per pair the shorter path is put on the rows (the scheme is symmetric in
+// its two arguments), so the wave streams the longer path's columns.  When
+// the rows exceed one wave's strips (64 lanes x R), the grid is processed in
+// row bands from the top: lane 63 of band b writes its bottom row (one
+// double per fine column) to a per-wave buffer, and lane 0 of band b+1
+// reads it as its upper neighbour instead of the boundary value 1.  Within a
+// band the mapping is the forward sweep's: lane strips, one coarse column per
+// step, DPP wave_shr:1 between lanes, coarse coefficients on the fly.
+#pragma once
+#include <math.h>
+
+#include "sweep_fwd_kernel.h"
+
+namespace sk {
+namespace pairk {
+
+using fwd::first_row;
+using fwd::from_prev_lane;
+using fwd::load_row;
+using fwd::n_inc;
+
+template <int R, int LAM, int D>
+__global__ __launch_bounds__(256) void pair_kernel(const PairArgs a) {
+  constexpr int DP = (D + 3) & ~3;
+  constexpr int S = 1 << LAM;
+  constexpr int CR = (R >> LAM) > 0 ? (R >> LAM) : 1;
+
+  const int lane = threadIdx.x & 63;
+  const int64_t slot = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  double* __restrict__ bb = a.bandbuf + slot * a.band_stride;
+  const int32_t count = *a.count;
+  const int32_t* __restrict__ order = a.order + (a.order_base ? *a.order_base : 0);
+
+  for (;;) {
+    // next pair of this class (one vector atomic per wave)
+    int32_t k = 0;
+    if (lane == 0) k = atomicAdd(a.counter, 1);
+    k = __shfl(k, 0, 64);
+    if (k >= count) break;
+    const int32_t pid = order[k];
+    const int64_t ix = a.gram_ny ? pid / a.gram_ny : pid;
+    const int64_t iy = a.gram_ny ? pid - ix * a.gram_ny : pid;
+    const int32_t mx = n_inc(a.x_n, a.x_len, ix), my = n_inc(a.y_n, a.y_len, iy);
+    if (mx < 0 || my < 0 || mx == 0 || my == 0) {
+      if (lane == 0) a.out[pid] = (mx < 0 || my < 0) ? __builtin_nanf("") : 1.0f;
+      continue;
+    }
+    const bool swap = mx > my;
+    const int32_t m = swap ? my : mx, n = swap ? mx : my;
+    const float* __restrict__ rinc =
+        swap ? a.incy + first_row(a.y_start, a.y_len, iy) * DP
+             : a.incx + first_row(a.x_start, a.x_len, ix) * DP;
+    const float* __restrict__ cinc =
+        swap ? a.incx + first_row(a.x_start, a.x_len, ix) * DP
+             : a.incy + first_row(a.y_start, a.y_len, iy) * DP;
+    const int M = m << LAM;
+    const int nb = (M + 64 * R - 1) / (64 * R);
+    const int off = nb * 64 * R - M;  // virtual rows above row 0, in the top band
+    const int32_t nsteps = (int32_t)sweep_steps(n);
+    double result = 1.0;
+
+    for (int band = 0; band < nb; ++band) {
+      // the previous band's bottom row (written by lane 63) must be visible
+      if (band > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const bool top = (band == 0), last = (band == nb - 1);
+      const int row0 = (band * 64 + lane) * R - off;
+      const int p0 = row0 >> LAM;
+      float dx[CR][D];
+#pragma unroll
+      for (int c = 0; c < CR; ++c) {
+        float t[DP];
+        if (p0 + c >= 0 && p0 + c < m) {
+          load_row<DP>(rinc + (int64_t)(p0 + c) * DP, t);
+        } else {
+#pragma unroll
+          for (int q = 0; q < DP; ++q) t[q] = 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < D; ++q) dx[c][q] = t[q];
+      }
+
+      double u[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[r] = 1.0;
+      double pub[S];
+#pragma unroll
+      for (int cc = 0; cc < S; ++cc) pub[cc] = 1.0;
+      double up_last = 1.0;
+      int32_t g = -lane;
+      const float* __restrict__ yp = cinc + (int64_t)g * DP;
+      // upper neighbours of lane 0: the boundary (top band) or the band above
+      auto bnd_load = [&](int32_t t, double (&v)[S]) {
+#pragma unroll
+        for (int cc = 0; cc < S; ++cc) v[cc] = top ? 1.0 : bb[(int64_t)t * S + cc];
+      };
+
+      float dyA[DP], dyB[DP], dyC[DP];
+      double bA[S], bB[S], bC[S];
+      load_row<DP>(yp, dyA);
+      load_row<DP>(yp + DP, dyB);
+      bnd_load(0, bA);
+      bnd_load(1, bB);
+
+      auto step = [&](int32_t t, float (&dy)[DP], float (&refill)[DP], double (&bv)[S],
+                      double (&brefill)[S]) {
+        load_row<DP>(yp + 2 * DP, refill);
+        bnd_load(t + 2, brefill);
+        float h32[CR];
+#pragma unroll
+        for (int c = 0; c < CR; ++c) {
+          float s = 0.0f;
+#pragma unroll
+          for (int q = 0; q < D; ++q) s = __builtin_fmaf(dx[c][q], dy[q], s);
+          h32[c] = s;
+        }
+        double up[S];
+#pragma unroll
+        for (int cc = 0; cc < S; ++cc) up[cc] = from_prev_lane(pub[cc], bv[cc]);
+
+        if ((uint32_t)g < (uint32_t)n) {
+          double gk[CR];
+#pragma unroll
+          for (int c = 0; c < CR; ++c) gk[c] = __builtin_fma((double)h32[c], a.scale, 1.0);
+          double v[R][S];
+#pragma unroll
+          for (int dgl = 0; dgl < R + S - 1; ++dgl) {
+#pragma unroll
+            for (int cc = 0; cc < S; ++cc) {
+              const int r = dgl - cc;
+              if (r < 0 || r >= R) continue;
+              const double A = (cc == 0) ? u[r] : v[r][cc - 1];
+              const double B = (r == 0) ? up[cc] : v[r - 1][cc];
+              const double C = (r == 0) ? ((cc == 0) ? up_last : up[cc - 1])
+                                        : ((cc == 0) ? u[r - 1] : v[r - 1][cc - 1]);
+              v[r][cc] = __builtin_fma(gk[(R >= S) ? (r >> LAM) : 0], A + B, -C);
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r) u[r] = v[r][S - 1];
+#pragma unroll
+          for (int cc = 0; cc < S; ++cc) pub[cc] = v[R - 1][cc];
+          up_last = up[S - 1];
+          if (lane == 63) {
+            if (!last) {
+#pragma unroll
+              for (int cc = 0; cc < S; ++cc) bb[(int64_t)g * S + cc] = pub[cc];
+            } else if (g == n - 1) {
+              result = u[R - 1];
+            }
+          }
+        }
+        ++g;
+        yp += DP;
+      };
+
+      for (int32_t t = 0; t < nsteps; t += 3) {
+        step(t, dyA, dyC, bA, bC);
+        step(t + 1, dyB, dyA, bB, bA);
+        step(t + 2, dyC, dyB, bC, bB);
+      }
+      if (!last) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    }
+    if (lane == 63) a.out[pid] = (float)result;
+  }
+}
+
+}  // namespace pairk
+}  // namespace sk

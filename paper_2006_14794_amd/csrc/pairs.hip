@@ -1,0 +1,134 @@
+// Planning and launch of independent pairs (pair_kernel.h): every pair is
+// classified by the rows it needs (shorter path, refined), the pairs of each
+// class are ordered longest first, and persistent waves take them from a
+// device queue.
+#include "internal.h"
+
+namespace sk {
+namespace {
+
+constexpr int kSortMax = 8192;  // pairs sorted in one workgroup's LDS
+
+__device__ __forceinline__ int32_t incs(const int32_t* plan, int32_t len, int64_t k) {
+  return plan ? plan[k] : len - 1;
+}
+
+// One workgroup.  Output: order[0 .. c_hi) = long-row class, order[c_hi ..
+// c_hi + c_lo) = short-row class, each by decreasing estimated cost; counts
+// {c_hi, c_lo}; both queue counters zeroed.
+__global__ __launch_bounds__(1024) void pair_plan_kernel(
+    const int32_t* __restrict__ x_n, int32_t x_len, const int32_t* __restrict__ y_n,
+    int32_t y_len, int32_t npairs, int32_t lam, int32_t rows_lo, int32_t rows_hi,
+    int64_t gram_ny, int32_t* __restrict__ order, int32_t* __restrict__ counts,
+    int32_t* __restrict__ counters) {
+  __shared__ unsigned long long keys[kSortMax];
+  __shared__ int32_t cnt[2];
+  if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  auto classify = [&](int32_t k, unsigned long long& cost) -> int {
+    const int64_t ix = gram_ny ? k / gram_ny : k, iy = gram_ny ? k - ix * gram_ny : k;
+    const int32_t mx = incs(x_n, x_len, ix), my = incs(y_n, y_len, iy);
+    if (mx <= 0 || my <= 0) {
+      cost = 0;
+      return 0;  // trivial or broken: instant, short class
+    }
+    const int64_t mn = mx < my ? mx : my, mxn = mx < my ? my : mx;
+    const int64_t M = mn << lam;
+    const int cls = M <= 64 * (int64_t)rows_lo ? 0 : 1;
+    const int64_t band_rows = 64 * (int64_t)(cls ? rows_hi : rows_lo);
+    const int64_t bands = (M + band_rows - 1) / band_rows;
+    cost = (unsigned long long)(bands * (mxn + 63));
+    return cls;
+  };
+  if (npairs <= kSortMax) {
+    int n2 = 1;
+    while (n2 < npairs) n2 <<= 1;
+    for (int32_t k = threadIdx.x; k < n2; k += blockDim.x) {
+      unsigned long long key = 0;  // padding sorts last
+      if (k < npairs) {
+        unsigned long long cost;
+        const int cls = classify(k, cost);
+        if (cost > (1ull << 45) - 1) cost = (1ull << 45) - 1;
+        // descending: long class first, then cost, then ascending index
+        key = (1ull << 63) | ((unsigned long long)cls << 62) | (cost << 16) |
+              (unsigned long long)(65535 - k);
+        atomicAdd(&cnt[cls], 1);
+      }
+      keys[k] = key;
+    }
+    __syncthreads();
+    // bitonic sort, descending
+    for (int size = 2; size <= n2; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+          const int j = i ^ stride;
+          if (j > i) {
+            const bool desc = (i & size) == 0;
+            const unsigned long long a = keys[i], b = keys[j];
+            if ((a < b) == desc) {
+              keys[i] = b;
+              keys[j] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x)
+      order[k] = 65535 - (int32_t)(keys[k] & 0xFFFFull);
+  } else {
+    // large batches: class compaction without ordering
+    __shared__ int32_t pos[2];
+    for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x) {
+      unsigned long long cost;
+      atomicAdd(&cnt[classify(k, cost)], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      pos[1] = 0;
+      pos[0] = cnt[1];
+    }
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x) {
+      unsigned long long cost;
+      const int cls = classify(k, cost);
+      order[atomicAdd(&pos[cls], 1)] = k;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    counts[0] = cnt[1];
+    counts[1] = cnt[0];
+    counters[0] = 0;
+    counters[1] = 0;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_pair_plan(const PairPlanArgs& p, hipStream_t stream) {
+  hipLaunchKernelGGL(pair_plan_kernel, dim3(1), dim3(1024), 0, stream, p.x_n, p.x_len, p.y_n,
+                     p.y_len, p.npairs, p.lam, p.rows_lo, p.rows_hi, p.gram_ny, p.order,
+                     p.counts, p.counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs(const PairArgs& a, int lam, int R, int d, int64_t max_waves,
+                        hipStream_t stream) {
+  auto f = reinterpret_cast<void (*)(const PairArgs)>(sweep_fn(kKernelPair, lam, R, d));
+  if (!f) return hipErrorInvalidValue;
+  int dev = 0, cus = 0, blocks_per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return hipErrorInvalidDevice;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, f, 256, 0) != hipSuccess)
+    return hipErrorInvalidValue;
+  if (blocks_per_cu < 1) blocks_per_cu = 1;
+  int64_t waves = (int64_t)cus * blocks_per_cu * 4;
+  if (waves > max_waves) waves = max_waves;  // max_waves: a multiple of 4 (wave slots)
+  const int64_t blocks = waves / 4 > 0 ? waves / 4 : 1;
+  hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace sk

@@ -8,15 +8,17 @@ namespace sk {
 SK_DECL(0, 0) SK_DECL(0, 1) SK_DECL(0, 2) SK_DECL(0, 3)
 SK_DECL(1, 0) SK_DECL(1, 1) SK_DECL(1, 2) SK_DECL(1, 3)
 SK_DECL(2, 0) SK_DECL(2, 1) SK_DECL(2, 2) SK_DECL(2, 3)
+SK_DECL(3, 0) SK_DECL(3, 1) SK_DECL(3, 2) SK_DECL(3, 3)
 #undef SK_DECL
 
 void* sweep_fn(int kind, int lam, int R, int d) {
   using Pick = void* (*)(int, int);
-  static const Pick table[3][4] = {
+  static const Pick table[4][4] = {
       {sweep_fn_k0_l0_, sweep_fn_k0_l1_, sweep_fn_k0_l2_, sweep_fn_k0_l3_},
       {sweep_fn_k1_l0_, sweep_fn_k1_l1_, sweep_fn_k1_l2_, sweep_fn_k1_l3_},
-      {sweep_fn_k2_l0_, sweep_fn_k2_l1_, sweep_fn_k2_l2_, sweep_fn_k2_l3_}};
-  if (kind < 0 || kind > 2 || lam < 0 || lam > 3) return nullptr;
+      {sweep_fn_k2_l0_, sweep_fn_k2_l1_, sweep_fn_k2_l2_, sweep_fn_k2_l3_},
+      {sweep_fn_k3_l0_, sweep_fn_k3_l1_, sweep_fn_k3_l2_, sweep_fn_k3_l3_}};
+  if (kind < 0 || kind > 3 || lam < 0 || lam > 3) return nullptr;
   return table[kind][lam](R, d);
 }
 

@@ -4,6 +4,8 @@
 #include "dispatch.h"
 #if SK_KIND == 2
 #include "sweep_bwd_kernel.h"
+#elif SK_KIND == 3
+#include "pair_kernel.h"
 #else
 #include "sweep_fwd_kernel.h"
 #endif
@@ -32,6 +34,17 @@ struct FwdStore {
   static Fn get() {
     if constexpr (sweep_fits(R, LAM, D))
       return reinterpret_cast<void*>(&fwd::sweep_kernel<R, LAM, D, true>);
+    else
+      return nullptr;
+  }
+};
+#elif SK_KIND == 3
+struct Pair {
+  using Fn = void*;
+  template <int R, int LAM, int D>
+  static Fn get() {
+    if constexpr (sweep_fits(R, LAM, D))
+      return reinterpret_cast<void*>(&pairk::pair_kernel<R, LAM, D>);
     else
       return nullptr;
   }
@@ -68,6 +81,8 @@ void* pick_fixed_lam(int R, int d) {
 void* SK_CAT(SK_CAT(sweep_fn_k0_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<FwdPlain>(R, d); }
 #elif SK_KIND == 1
 void* SK_CAT(SK_CAT(sweep_fn_k1_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<FwdStore>(R, d); }
+#elif SK_KIND == 3
+void* SK_CAT(SK_CAT(sweep_fn_k3_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Pair>(R, d); }
 #else
 void* SK_CAT(SK_CAT(sweep_fn_k2_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Adjoint>(R, d); }
 #endif

@@ -91,17 +91,14 @@ def test_gram_several_tiles_and_ragged_tail():
     assert mixed_err(got, ref).max() <= TOL
 
 
-def test_row_capacity_limit_exactly_filled():
-    # M = 64 lanes x 32 rows: the largest x side of the one-wave sweep at lambda = 1
-    rng = np.random.default_rng(5)
-    x = workloads.random_paths(7, 1, 1025, 4)
-    y = workloads.random_paths(8, 1, 40, 4)
-    got = sk.sigkernel_pair(cuda(x), cuda(y), 1).cpu().numpy()
-    ref = oracle.solve(x[0].astype(np.float64), y[0].astype(np.float64), 1)
-    assert mixed_err(got[0], ref) <= 1e-5
-    x2 = workloads.random_paths(9, 1, 1026, 4)
-    with pytest.raises(sk.SigKernelError):
-        sk.sigkernel_pair(cuda(x2), cuda(y), 1)
+def test_row_capacity_limit_exactly_filled_and_exceeded():
+    # M = 64 lanes x 32 rows exactly, then one coarse row more (a second band)
+    for L in (1025, 1026):
+        x = workloads.random_paths(7, 1, L, 4)
+        y = workloads.random_paths(8, 1, L + 3, 4)
+        got = sk.sigkernel_pair(cuda(x), cuda(y), 1).cpu().numpy()
+        ref = oracle.solve(x[0].astype(np.float64), y[0].astype(np.float64), 1)
+        assert mixed_err(got[0], ref) <= 1e-5
 
 
 @pytest.mark.parametrize("lam", [0, 2])
