@@ -41,10 +41,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-pairs", type=int, default=0,
                     help="pairs of the workload timed on the CPU oracle (0: auto)")
-    ap.add_argument("--workload", choices=["gram", "mmd", "ragged"], default="gram",
+    ap.add_argument("--workload", choices=["gram", "mmd", "ragged", "increment_gram"],
+                    default="gram",
                     help="gram: the 128 x 128 Gram batch (default, the reported metric); "
                          "mmd: unbiased MMD^2 of 64 vs 64 512-point paths with its gradient; "
-                         "ragged: 4096 independent pairs of uneven lengths")
+                         "ragged: 4096 independent pairs of uneven lengths; "
+                         "increment_gram: the coarse Gram of the Gram batch on the matrix cores")
     return ap.parse_args()
 
 
@@ -183,6 +185,37 @@ def bench_ragged(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_increment_gram(args):
+    """The coarse increment Gram G0 of the 128 x 128 Gram batch (255 x 255 per
+    pair, d = 9) on the matrix cores, written to HBM: bound by the 4-byte
+    write per coarse cell."""
+    import torch
+    import paper_2006_14794_amd as sk
+    import workloads
+    X, Y = workloads.gram_batch()
+    Xt, Yt = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    nx, L, d = X.shape
+    out = torch.empty((nx, Y.shape[0], L - 1, L - 1), dtype=torch.float32, device="cuda")
+    recs = {}
+    for prec in ("f32", "bf16"):
+        def step():
+            sk.sigkernel_increment_gram(Xt, Yt, precision=prec, out=out)
+        per, wall = time_steps(step, args.steps, args.warmup)
+        avg = float(np.mean(per)) / 1e3
+        nbytes = out.numel() * 4 + (X.size + Y.size) * 4
+        recs[prec] = {"ms": avg * 1e3, "hbm_GBps": nbytes / avg / 1e9,
+                      "frac_of_8TBps": nbytes / avg / 8e12}
+    rec = {"metric": "increment Gram bytes written/s", "value": recs["f32"]["hbm_GBps"],
+           "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": recs["f32"]["ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "coarse Gram of 128 x 128 pairs, 255 x 255 each, d = 9"},
+           "roofline": {"bound": "hbm", "achieved": recs["f32"]["hbm_GBps"], "peak": 8000.0,
+                        "unit": "GB/s", "frac": recs["f32"]["frac_of_8TBps"], "traffic": None},
+           "precisions": recs}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -194,6 +227,9 @@ def main():
         return
     if args.workload == "ragged":
         bench_ragged(args)
+        return
+    if args.workload == "increment_gram":
+        bench_increment_gram(args)
         return
 
     import torch

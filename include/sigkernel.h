@@ -80,7 +80,10 @@ typedef struct sk_paths {
 enum {
     SK_SYMMETRIC = 1u << 0,   /* gram only: X and Y are the same batch; solve a <= b and mirror */
     SK_NO_DIAG   = 1u << 1,   /* gram only, with SK_SYMMETRIC: write 0 on the diagonal         */
-    SK_MMD2_GRAD = 1u << 2    /* mmd2 only: also write the gradient with respect to X          */
+    SK_MMD2_GRAD = 1u << 2,   /* mmd2 only: also write the gradient with respect to X          */
+    SK_GRAM_BF16 = 1u << 3,   /* pair / gram: increments rounded to bfloat16 before the inner
+                                 products (16-bit inputs, float32 accumulation)                */
+    SK_GRAM_F16  = 1u << 4    /* pair / gram: the same with IEEE half                          */
 };
 
 /*
@@ -127,6 +130,25 @@ sk_status sigkernel_gram(const sk_paths *X, const sk_paths *Y, int32_t dyadic_or
 sk_status sigkernel_gram_backward(const sk_paths *X, const sk_paths *Y, int32_t dyadic_order,
                                   uint32_t flags, const float *dK, float *dX, float *dY,
                                   void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * sigkernel_increment_gram -- the coarse increment inner products of Section
+ * 3.1 (piecewise-linear case) on the matrix cores:
+ *   G0[pair][p][q] = <x_{p+1} - x_p, y_{q+1} - y_q>,  p < x.len - 1, q < y.len - 1,
+ * written to HBM for every pair: gram = 1 enumerates (a, b) as a * Y->n_paths
+ * + b, gram = 0 the pairs (x_k, y_k) (equal batch sizes).
+ *  - Uniform batches of at most 16 channels; G0: DEVICE
+ *    float[pairs][X->len - 1][Y->len - 1].
+ *  - flags: SK_GRAM_BF16 / SK_GRAM_F16 round the increments to 16 bits (the
+ *    products and sums stay float32); otherwise float32 throughout.
+ *  - No workspace.  Paths with one point give an empty G0 (nothing written).
+ * The sweeps of sigkernel_pair / sigkernel_gram do not read G0 from memory:
+ * they form the same inner products on the fly in registers, which avoids
+ * writing and re-reading 4 bytes per coarse cell; this entry point serves
+ * callers that need the coarse Gram itself.
+ */
+sk_status sigkernel_increment_gram(const sk_paths *X, const sk_paths *Y, int32_t gram,
+                                   uint32_t flags, float *G0, void *stream);
 
 /*
  * sigkernel_mmd2 -- unbiased MMD^2 between the laws of two batches of paths

@@ -9,12 +9,13 @@ is the thin Python binding; it never computes anything on the CPU.
 """
 from ._lib import SK_NO_DIAG, SK_SYMMETRIC, SigKernelError, load, status_string, version
 from .api import (RaggedPaths, SigKernelGram, SigKernelGramSymmetric, SigKernelMMD2, gram, mmd2,
-                  sigkernel_gram, sigkernel_gram_backward, sigkernel_mmd2, sigkernel_pair,
+                  sigkernel_gram, sigkernel_gram_backward, sigkernel_increment_gram, sigkernel_mmd2,
+                  sigkernel_pair,
                   workspace_bytes)
 
 __all__ = [
     "RaggedPaths", "SigKernelError", "SigKernelGram", "SigKernelGramSymmetric", "gram", "load",
-    "SigKernelMMD2", "mmd2", "sigkernel_mmd2",
+    "SigKernelMMD2", "mmd2", "sigkernel_mmd2", "sigkernel_increment_gram",
     "sigkernel_gram", "sigkernel_gram_backward", "sigkernel_pair",
     "status_string", "version", "workspace_bytes",
     "SK_SYMMETRIC", "SK_NO_DIAG",

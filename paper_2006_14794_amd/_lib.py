@@ -25,6 +25,8 @@ SK_ERR_UNSUPPORTED = -7
 SK_SYMMETRIC = 1 << 0
 SK_NO_DIAG = 1 << 1
 SK_MMD2_GRAD = 1 << 2
+SK_GRAM_BF16 = 1 << 3
+SK_GRAM_F16 = 1 << 4
 
 SK_OP_PAIR = 0
 SK_OP_GRAM = 1
@@ -37,6 +39,7 @@ EXPORTED = (
     "sigkernel_gram",
     "sigkernel_gram_backward",
     "sigkernel_mmd2",
+    "sigkernel_increment_gram",
     "sigkernel_workspace_bytes",
     "sigkernel_status_string",
     "sigkernel_version",
@@ -83,6 +86,8 @@ def load():
     lib.sigkernel_gram_backward.restype = i32
     lib.sigkernel_mmd2.argtypes = [P, P, i32, u32, vp, vp, vp, sz, vp]
     lib.sigkernel_mmd2.restype = i32
+    lib.sigkernel_increment_gram.argtypes = [P, P, i32, u32, vp, vp]
+    lib.sigkernel_increment_gram.restype = i32
     lib.sigkernel_workspace_bytes.argtypes = [i32, P, P, i32, u32]
     lib.sigkernel_workspace_bytes.restype = sz
     lib.sigkernel_status_string.argtypes = [i32]

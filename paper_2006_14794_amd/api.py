@@ -97,14 +97,25 @@ def _workspace(nbytes: int, device, ws: Optional[torch.Tensor]) -> torch.Tensor:
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
 
 
+_GRAM_PRECISION = {"f32": 0, "bf16": _lib.SK_GRAM_BF16, "f16": _lib.SK_GRAM_F16}
+
+
+def _gram_flag(gram_precision: str) -> int:
+    if gram_precision not in _GRAM_PRECISION:
+        raise ValueError("gram_precision must be 'f32', 'bf16' or 'f16'")
+    return _GRAM_PRECISION[gram_precision]
+
+
 def sigkernel_pair(x: PathsLike, y: PathsLike, dyadic_order: int = 0, *,
-                   out: Optional[torch.Tensor] = None,
+                   gram_precision: str = "f32", out: Optional[torch.Tensor] = None,
                    workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """out[k] = k_hat(x_k, y_k) of the explicit scheme on P_lambda."""
+    """out[k] = k_hat(x_k, y_k) of the explicit scheme on P_lambda.
+    ``gram_precision`` 'bf16' / 'f16' rounds the increments to 16 bits before
+    their inner products (float32 accumulation)."""
     lib = _lib.load()
     dev = _device(x)
     n = _n_paths(x)
-    flags = 0
+    flags = _gram_flag(gram_precision)
     sx, sy = _describe(x), _describe(y)
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=dev)
@@ -120,7 +131,7 @@ def sigkernel_pair(x: PathsLike, y: PathsLike, dyadic_order: int = 0, *,
 
 def sigkernel_gram(X: PathsLike, Y: Optional[PathsLike] = None, dyadic_order: int = 0, *,
                    symmetric: bool = False, no_diag: bool = False,
-                   out: Optional[torch.Tensor] = None,
+                   gram_precision: str = "f32", out: Optional[torch.Tensor] = None,
                    workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
     """K[a, b] = k_hat(X_a, Y_b).  ``symmetric=True`` (Y omitted or X itself)
     solves a <= b only and mirrors; ``no_diag`` then writes 0 on the diagonal."""
@@ -131,7 +142,7 @@ def sigkernel_gram(X: PathsLike, Y: Optional[PathsLike] = None, dyadic_order: in
         raise ValueError("symmetric Gram needs Y to be X")
     dev = _device(X)
     nx, ny = _n_paths(X), _n_paths(Y)
-    flags = 0
+    flags = _gram_flag(gram_precision)
     if symmetric:
         flags |= _lib.SK_SYMMETRIC
         if no_diag:
@@ -271,3 +282,22 @@ class SigKernelMMD2(torch.autograd.Function):
 def mmd2(X: torch.Tensor, Y: torch.Tensor, dyadic_order: int = 0) -> torch.Tensor:
     """Differentiable (in X) unbiased signature-kernel MMD^2."""
     return SigKernelMMD2.apply(X, Y, dyadic_order)
+
+
+def sigkernel_increment_gram(X: torch.Tensor, Y: torch.Tensor, *, gram: bool = True,
+                             precision: str = "f32",
+                             out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """G0 = <x_{p+1} - x_p, y_{q+1} - y_q> of every pair on the matrix cores:
+    [nx, ny, Lx-1, Ly-1] (gram) or [n, Lx-1, Ly-1] (pairs)."""
+    lib = _lib.load()
+    sx, sy = _describe(X), _describe(Y)
+    m, n = int(X.shape[1]) - 1, int(Y.shape[1]) - 1
+    shape = (int(X.shape[0]), int(Y.shape[0]), m, n) if gram else (int(X.shape[0]), m, n)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=X.device)
+    st = lib.sigkernel_increment_gram(ctypes.byref(sx), ctypes.byref(sy), 1 if gram else 0,
+                                      _gram_flag(precision),
+                                      out.data_ptr() if out.numel() else None,
+                                      _stream_ptr(X.device))
+    _lib.check(st, "sigkernel_increment_gram")
+    return out

@@ -169,7 +169,14 @@ BackwardPlan backward_plan(const sk_paths* X, const sk_paths* Y, int32_t lam, ui
 
 
 
+int rounding_of(uint32_t flags) {
+  if (flags & SK_GRAM_BF16) return sk::kRoundBf16;
+  if (flags & SK_GRAM_F16) return sk::kRoundF16;
+  return sk::kRoundNone;
+}
+
 sk_status check_flags(uint32_t flags, uint32_t allowed) {
+  if ((flags & SK_GRAM_BF16) && (flags & SK_GRAM_F16)) return SK_ERR_FLAGS;
   if (flags & ~allowed) return SK_ERR_FLAGS;
   if ((flags & SK_NO_DIAG) && !(flags & SK_SYMMETRIC)) return SK_ERR_FLAGS;
   return SK_OK;
@@ -177,7 +184,7 @@ sk_status check_flags(uint32_t flags, uint32_t allowed) {
 
 // gram: every (a, b) of the two batches, out[a * ny + b]; else pairs (x_k, y_k)
 sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* out, void* ws,
-                    size_t ws_bytes, hipStream_t stream, bool gram) {
+                    size_t ws_bytes, hipStream_t stream, bool gram, int rounding) {
   const int d = X->dim;
   const int dp = sk::padded_dim(d);
   const PairLayout PL = pair_layout(X, Y, lam, gram);
@@ -196,9 +203,11 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* ou
   const sk::Batch bx = to_batch(X), by = to_batch(Y);
   if (X->offsets && sk::launch_plan(bx, px, stream) != hipSuccess) return SK_ERR_HIP;
   if (Y->offsets && sk::launch_plan(by, py, stream) != hipSuccess) return SK_ERR_HIP;
-  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, 1.0f, dp, incx, stream) != hipSuccess)
+  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, 1.0f, dp, incx, stream, rounding) !=
+      hipSuccess)
     return SK_ERR_HIP;
-  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream) != hipSuccess)
+  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream, rounding) !=
+      hipSuccess)
     return SK_ERR_HIP;
   int32_t* order = reinterpret_cast<int32_t*>(base + PL.order);
   int32_t* counts = reinterpret_cast<int32_t*>(base + PL.counts);
@@ -251,7 +260,8 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* ou
 
 sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t flags,
                       float* out, void* ws, size_t ws_bytes, hipStream_t stream, int mode) {
-  if (mode == 0) return run_pairs(X, Y, lam, out, ws, ws_bytes, stream, false);
+  const int rounding = rounding_of(flags);
+  if (mode == 0) return run_pairs(X, Y, lam, out, ws, ws_bytes, stream, false, rounding);
   const int d = X->dim;
   const int dp = sk::padded_dim(d);
   const int64_t fine_rows = (int64_t)(X->len - 1) << lam;
@@ -260,7 +270,7 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_
     // x paths taller than one wave's strips: every (a, b) through the
     // persistent pair kernel with row bands (a symmetric Gram is filled in
     // both halves by solving both)
-    const sk_status st = run_pairs(X, Y, lam, out, ws, ws_bytes, stream, true);
+    const sk_status st = run_pairs(X, Y, lam, out, ws, ws_bytes, stream, true, rounding);
     if (st == SK_OK && mode == 2 && (flags & SK_NO_DIAG) &&
         sk::launch_zero_diag(out, X->n_paths, stream) != hipSuccess)
       return SK_ERR_HIP;
@@ -281,9 +291,11 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_
   if (Y->offsets && sk::launch_plan(by, py, stream) != hipSuccess) return SK_ERR_HIP;
   // h = G0 / 2^(2 lam + 1): fold the exact power-of-two scale into the x side
   const float scale = ldexpf(1.0f, -(2 * lam + 1));
-  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, scale, dp, incx, stream) != hipSuccess)
+  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, scale, dp, incx, stream, rounding) !=
+      hipSuccess)
     return SK_ERR_HIP;
-  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream) != hipSuccess)
+  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream, rounding) !=
+      hipSuccess)
     return SK_ERR_HIP;
 
   sk::SweepArgs a{};
@@ -408,7 +420,7 @@ sk_status sigkernel_pair(const sk_paths* x, const sk_paths* y, int32_t dyadic_or
   if ((x->n_paths > 0 && !x->points) || (y->n_paths > 0 && !y->points)) return SK_ERR_NULL;
   if (x->dim != y->dim || x->n_paths != y->n_paths) return SK_ERR_SHAPE;
   if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
-  if (sk_status f = check_flags(flags, 0)) return f;
+  if (sk_status f = check_flags(flags, SK_GRAM_BF16 | SK_GRAM_F16)) return f;
   if (x->n_paths == 0) return SK_OK;
   if (!ws) return SK_ERR_WORKSPACE;
   return run_forward(x, y, dyadic_order, flags, out, ws, ws_bytes,
@@ -423,7 +435,8 @@ sk_status sigkernel_gram(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
   if ((X->n_paths > 0 && !X->points) || (Y->n_paths > 0 && !Y->points)) return SK_ERR_NULL;
   if (X->dim != Y->dim) return SK_ERR_SHAPE;
   if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
-  if (sk_status f = check_flags(flags, SK_SYMMETRIC | SK_NO_DIAG)) return f;
+  if (sk_status f = check_flags(flags, SK_SYMMETRIC | SK_NO_DIAG | SK_GRAM_BF16 | SK_GRAM_F16))
+    return f;
   if ((flags & SK_SYMMETRIC) &&
       (X->points != Y->points || X->offsets != Y->offsets || X->n_paths != Y->n_paths ||
        X->len != Y->len))
@@ -432,6 +445,34 @@ sk_status sigkernel_gram(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
   if (!ws) return SK_ERR_WORKSPACE;
   return run_forward(X, Y, dyadic_order, flags, K, ws, ws_bytes,
                      static_cast<hipStream_t>(stream), (flags & SK_SYMMETRIC) ? 2 : 1);
+}
+
+sk_status sigkernel_increment_gram(const sk_paths* X, const sk_paths* Y, int32_t gram,
+                                  uint32_t flags, float* G0, void* stream) {
+  if (!X || !Y) return SK_ERR_NULL;
+  if (!valid_batch(X) || !valid_batch(Y) || X->dim != Y->dim) return SK_ERR_SHAPE;
+  if (gram != 0 && gram != 1) return SK_ERR_FLAGS;
+  if (!gram && X->n_paths != Y->n_paths) return SK_ERR_SHAPE;
+  if (sk_status f = check_flags(flags, SK_GRAM_BF16 | SK_GRAM_F16)) return f;
+  if (X->offsets || Y->offsets) return SK_ERR_UNSUPPORTED;
+  const int64_t pairs = gram ? X->n_paths * Y->n_paths : X->n_paths;
+  if (pairs == 0 || X->len < 2 || Y->len < 2) return SK_OK;
+  if (!G0 || !X->points || !Y->points) return SK_ERR_NULL;
+  if ((int64_t)((X->len + 30) / 32) > 65535 || X->dim > 16) return SK_ERR_UNSUPPORTED;
+  sk::GramArgs a{};
+  a.x = X->points;
+  a.y = Y->points;
+  a.x_len = X->len;
+  a.y_len = Y->len;
+  a.d = X->dim;
+  a.nx = X->n_paths;
+  a.ny = Y->n_paths;
+  a.gram = gram;
+  a.g0 = G0;
+  const hipError_t e =
+      sk::launch_gram_mfma(a, rounding_of(flags), static_cast<hipStream_t>(stream));
+  if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;
+  return e == hipSuccess ? SK_OK : SK_ERR_HIP;
 }
 
 sk_status sigkernel_mmd2(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,

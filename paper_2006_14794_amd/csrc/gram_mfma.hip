@@ -1,0 +1,122 @@
+// Coarse increment Gram G0[p][q] = <x_{p+1} - x_p, y_{q+1} - y_q> (Section
+// 3.1, piecewise-linear case) of every pair of two uniform batches, written
+// to HBM, on the matrix cores: a dense contraction over the channels.
+//
+// A workgroup owns 32 whole rows of one pair's G0 (a contiguous region of
+// HBM).  It stages the points of those rows and of 256-column chunks of the
+// other path in LDS, its four waves take turns over the chunk's 32-column
+// tiles, and a wave accumulates a 32 x 32 tile in sixteen float32 registers
+// per lane:
+//   float32 inputs: v_mfma_f32_32x32x2_f32, two channels per instruction;
+//   bf16 / fp16 inputs: v_mfma_f32_32x32x16_{bf16,f16}, sixteen channels per
+//   instruction (increments rounded to nearest even, products and sums in
+//   float32).
+// Operands are the increments themselves, formed from the staged points.  Lane l supplies row (l mod 32) of the x tile and column (l mod 32)
+// of the y tile; its half (l / 32) selects the channel slice.  Accumulator
+// register r of lane l holds row 8 (r / 4) + 4 (l / 32) + (r mod 4), column
+// l mod 32.  Tiles go to LDS first; the workgroup then writes each row's
+// chunk as one run of consecutive floats.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "internal.h"
+
+namespace sk {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kChunk = 256;    // columns per output chunk
+constexpr int kMaxDim = 16;    // channels staged in LDS (larger d: not staged)
+
+template <int PREC>  // 0: float32, 1: bf16, 2: fp16
+__global__ __launch_bounds__(256) void gram_mfma_kernel(const GramArgs a) {
+  __shared__ float xs[33 * kMaxDim];           // 33 points: 32 increments
+  __shared__ float ys[(kChunk + 1) * kMaxDim];  // a chunk's 257 points
+  __shared__ float tile[32 * kChunk];           // 32 rows x 256 columns of G0
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int64_t pair = blockIdx.x;
+  const int64_t ia = a.gram ? pair / a.ny : pair;
+  const int64_t ib = a.gram ? pair - ia * a.ny : pair;
+  const int32_t m = a.x_len - 1, n = a.y_len - 1, d = a.d;
+  const int32_t p0 = blockIdx.y * 32;  // 32 whole rows of the pair
+  const int32_t rows = m - p0 < 32 ? m - p0 : 32;
+  const float* __restrict__ xp = a.x + (ia * (int64_t)a.x_len + p0) * d;
+  const float* __restrict__ yq = a.y + ib * (int64_t)a.y_len * d;
+  float* __restrict__ g = a.g0 + pair * (int64_t)m * n + (int64_t)p0 * n;
+  for (int e = threadIdx.x; e < (rows + 1) * d; e += blockDim.x) xs[e] = xp[e];
+  const int32_t row = lane & 31, half = lane >> 5;
+  auto xinc = [&](int k) -> float {
+    return (row < rows && k < d) ? xs[(row + 1) * d + k] - xs[row * d + k] : 0.0f;
+  };
+  for (int32_t c0 = 0; c0 < n; c0 += kChunk) {
+    const int32_t cw = n - c0 < kChunk ? n - c0 : kChunk;
+    __syncthreads();  // xs ready / the previous chunk's tile and ys consumed
+    for (int e = threadIdx.x; e < (cw + 1) * d; e += blockDim.x) ys[e] = yq[(int64_t)c0 * d + e];
+    __syncthreads();
+    for (int32_t t0 = wid * 32; t0 < cw; t0 += 128) {
+      auto yinc = [&](int k) -> float {
+        const int c = t0 + row;
+        return (c < cw && k < d) ? ys[(c + 1) * d + k] - ys[c * d + k] : 0.0f;
+      };
+      f32x16 acc = {};
+      if constexpr (PREC == 0) {
+        for (int k0 = 0; k0 < d; k0 += 2)
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xinc(k0 + half), yinc(k0 + half), acc, 0, 0,
+                                                      0);
+      } else {
+        for (int k0 = 0; k0 < d; k0 += 16) {
+          if constexpr (PREC == 1) {
+            bf16x8 A, B;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              A[j] = (__bf16)xinc(k0 + half * 8 + j);
+              B[j] = (__bf16)yinc(k0 + half * 8 + j);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc, 0, 0, 0);
+          } else {
+            f16x8 A, B;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              A[j] = (_Float16)xinc(k0 + half * 8 + j);
+              B[j] = (_Float16)yinc(k0 + half * 8 + j);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, B, acc, 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        tile[(8 * (r >> 2) + 4 * half + (r & 3)) * kChunk + t0 + row] = acc[r];
+    }
+    __syncthreads();
+    // rows x cw block of G0: runs of cw consecutive floats per row
+    for (int e = threadIdx.x; e < rows * cw; e += blockDim.x) {
+      const int r = e / cw, c = e - r * cw;
+      g[(int64_t)r * n + c0 + c] = tile[r * kChunk + c];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gram_mfma(const GramArgs& a, int precision, hipStream_t stream) {
+  const int32_t m = a.x_len - 1, n = a.y_len - 1;
+  const int64_t pairs = a.gram ? a.nx * a.ny : a.nx;
+  if (m <= 0 || n <= 0 || pairs == 0) return hipSuccess;
+  const int64_t row_blocks = (m + 31) / 32;
+  if (row_blocks > 65535 || pairs > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)pairs, (unsigned)row_blocks, 1);
+  if (precision == kRoundBf16)
+    hipLaunchKernelGGL(gram_mfma_kernel<1>, grid, dim3(256), 0, stream, a);
+  else if (precision == kRoundF16)
+    hipLaunchKernelGGL(gram_mfma_kernel<2>, grid, dim3(256), 0, stream, a);
+  else
+    hipLaunchKernelGGL(gram_mfma_kernel<0>, grid, dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace sk

@@ -2,6 +2,9 @@
 // PDE coefficient is the inner product of the two segment increments), laid
 // out densely: the increments of consecutive paths are consecutive rows, so a
 // sweep that streams several y paths reads one contiguous row range.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
 #include "internal.h"
 
 namespace sk {
@@ -51,7 +54,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(const int64_t* __restrict__ 
 __global__ __launch_bounds__(256) void increments_kernel(
     const float* __restrict__ pts, const int64_t* __restrict__ off,
     const int32_t* __restrict__ plan_n, const int64_t* __restrict__ plan_start, int32_t len,
-    int64_t n_paths, int32_t d, int32_t dpad, float scale, float* __restrict__ incr) {
+    int64_t n_paths, int32_t d, int32_t dpad, float scale, int32_t rounding,
+    float* __restrict__ incr) {
   const int64_t k = blockIdx.x;
   if (k >= n_paths) return;
   int64_t pstart, dstart;
@@ -74,7 +78,12 @@ __global__ __launch_bounds__(256) void increments_kernel(
     if (c < d) {
       const float a = pts[(pstart + p + 1) * d + c];
       const float b = pts[(pstart + p) * d + c];
-      v = (a - b) * scale;  // power-of-two scale: exact
+      v = a - b;
+      // 16-bit inputs of the inner products (round to nearest even); the
+      // products and their sums stay float32
+      if (rounding == kRoundBf16) v = __bfloat162float(__float2bfloat16(v));
+      if (rounding == kRoundF16) v = __half2float(__float2half(v));
+      v *= scale;  // power-of-two scale: exact
     }
     incr[(dstart + p) * dpad + c] = v;
   }
@@ -104,12 +113,12 @@ hipError_t launch_plan(const Batch& b, PathPlan plan, hipStream_t stream) {
 }
 
 hipError_t launch_increments(const Batch& b, const PathPlan* plan, float scale, int dpad,
-                             float* incr, hipStream_t stream) {
+                             float* incr, hipStream_t stream, int rounding) {
   if (b.n_paths == 0 || (!b.offsets && b.len < 2)) return hipSuccess;
   hipLaunchKernelGGL(increments_kernel, dim3((unsigned)b.n_paths), dim3(256), 0, stream,
                      b.points, b.offsets, plan ? plan->n : nullptr,
                      plan ? plan->start : nullptr, b.len, b.n_paths, b.dim, dpad, scale,
-                     incr);
+                     rounding, incr);
   return hipGetLastError();
 }
 

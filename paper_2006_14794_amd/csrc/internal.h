@@ -37,9 +37,12 @@ hipError_t launch_plan(const Batch& b, PathPlan plan, hipStream_t stream);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t stream);
 
 // Dense padded increments: row start[k] + p holds scale * (x_{p+1} - x_p),
-// p < n[k], zero-padded to `dpad` channels.  scale is a power of two.
+// p < n[k], zero-padded to `dpad` channels.  scale is a power of two.  With
+// rounding kRoundBf16 / kRoundF16 each increment is first rounded to that
+// 16-bit format (the inner products then see 16-bit inputs, float32 sums).
+enum { kRoundNone = 0, kRoundBf16 = 1, kRoundF16 = 2 };
 hipError_t launch_increments(const Batch& b, const PathPlan* plan, float scale, int dpad,
-                             float* incr, hipStream_t stream);
+                             float* incr, hipStream_t stream, int rounding = kRoundNone);
 
 // Work description of one forward sweep launch.
 struct SweepArgs {
@@ -150,6 +153,18 @@ hipError_t launch_pair_plan(const PairPlanArgs& p, hipStream_t stream);
 // Persistent launch: min(max_waves, resident waves) wavefronts.
 hipError_t launch_pairs(const PairArgs& a, int lam, int rows_per_lane, int dim,
                         int64_t max_waves, hipStream_t stream);
+
+// Increment Gram of uniform batches on the matrix cores (gram_mfma.hip).
+struct GramArgs {
+  const float* x;           // points [nx][x_len][d]
+  const float* y;           // points [ny][y_len][d]
+  int32_t x_len, y_len, d;
+  int64_t nx, ny;
+  int32_t gram;             // 1: every (a, b), pair index a ny + b; 0: pairs (x_k, y_k)
+  float* g0;                // [pairs][x_len - 1][y_len - 1]
+};
+// precision: kRoundNone (float32 MFMA), kRoundBf16, kRoundF16
+hipError_t launch_gram_mfma(const GramArgs& a, int precision, hipStream_t stream);
 
 // Compiled sweep kernels by kind, dyadic order, rows per lane and channels
 // (nullptr when the configuration is not compiled).
