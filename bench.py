@@ -39,8 +39,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch the library call every step instead of replaying its hipGraph")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in launch rules instead of autotuning (untimed) first")
     ap.add_argument("--cpu-sample-pairs", type=int, default=0,
-                    help="pairs of the workload timed on the CPU oracle (0: auto)")
+                    help="pairs of the workload timed on the CPU oracle (0: all)")
     ap.add_argument("--workload", choices=["gram", "mmd", "ragged", "increment_gram"],
                     default="gram",
                     help="gram: the 128 x 128 Gram batch (default, the reported metric); "
@@ -58,25 +62,32 @@ def sweep_ops_per_cell(d: int, lam: int) -> float:
     return 2.0 + 0.5 * d / float(4 ** lam)
 
 
-def cpu_baseline(X, Y, lam, n_sample, K_gpu):
-    """Time the FP64 oracle on a seeded sample of the workload's pairs, on all
-    host threads, and report the GPU output's error on the same pairs."""
+def cpu_baseline(X, Y, lam, n_sample, K_gpu, repeats=3):
+    """Time the FP64 oracle on the workload's pairs (all of them unless
+    n_sample is given: a seeded sample), on all host threads, median of
+    ``repeats`` runs, and report the GPU output's error on the same pairs."""
     import oracle
-    rng = np.random.default_rng(1)
     nx, ny = X.shape[0], Y.shape[0]
-    idx = rng.choice(nx * ny, size=n_sample, replace=False)
+    if n_sample and n_sample < nx * ny:
+        idx = np.random.default_rng(1).choice(nx * ny, size=n_sample, replace=False)
+    else:
+        idx = np.arange(nx * ny)
     xs = [X[i // ny].astype(np.float64) for i in idx]
     ys = [Y[i % ny].astype(np.float64) for i in idx]
     threads = oracle.max_threads()
     oracle.pairs(xs[:8], ys[:8], lam)  # load + warm
-    t0 = time.perf_counter()
-    ref = oracle.pairs(xs, ys, lam, nthreads=threads)
-    dt = time.perf_counter() - t0
-    cells = n_sample * ((X.shape[1] - 1) << lam) * ((Y.shape[1] - 1) << lam)
+    times = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        ref = oracle.pairs(xs, ys, lam, nthreads=threads)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    cells = len(idx) * ((X.shape[1] - 1) << lam) * ((Y.shape[1] - 1) << lam)
     err = np.abs(K_gpu.reshape(-1)[idx] - ref) / np.maximum(1.0, np.abs(ref))
+    what = (f"all {nx * ny} Gram pairs" if len(idx) == nx * ny
+            else f"{len(idx)} of the {nx * ny} Gram pairs (seeded)")
     return {"value": cells / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_sample} of the {nx * ny} Gram pairs (seeded), all host threads, "
-                      f"{dt:.2f} s",
+            "sample": f"{what}, all host threads, median of {repeats} runs of {dt:.2f} s",
             "gpu_max_err_on_sample": float(err.max())}
 
 
@@ -100,6 +111,15 @@ def time_steps(fn, steps, warmup):
     return [s.elapsed_time(e) for s, e in zip(starts, ends)], wall
 
 
+def make_step(call, capture, eager):
+    """The timed step: a replay of the call's hipGraph (captured once, before
+    the warm-up), or with ``eager`` the call itself."""
+    if eager:
+        return call, "eager"
+    g = capture()
+    return g.replay, "hipGraph replay"
+
+
 def bench_mmd(args):
     """Unbiased MMD^2 between 64 generated paths (the parameters) and 64 OU
     targets, 512 points in R^4, dyadic order 1: value and gradient in X."""
@@ -114,9 +134,11 @@ def bench_mmd(args):
     Xt, Yt = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
     ws = torch.empty(sk.workspace_bytes(3, Xt, Yt, lam, 4), dtype=torch.uint8, device=dev)
 
-    def step():
+    def call():
         sk.sigkernel_mmd2(Xt, Yt, lam, grad=True, workspace=ws)
 
+    step, launch = make_step(call, lambda: sk.capture_mmd2(Xt, Yt, lam, grad=True)[0],
+                             args.eager)
     per, wall = time_steps(step, args.steps, args.warmup)
     ms = wall * 1e3 / args.steps
     cells = ((L - 1) << lam) ** 2
@@ -132,7 +154,7 @@ def bench_mmd(args):
                                "d=4, dyadic order 1, value + gradient in X",
                    "forward_pairs": fwd_pairs, "adjoint_pairs": bwd_pairs,
                    "fine_cells_per_pair": cells},
-        "avg_event_ms": float(np.mean(per)),
+        "avg_event_ms": float(np.mean(per)), "launch": launch,
     }
     print(json.dumps(rec), flush=True)
 
@@ -148,12 +170,17 @@ def bench_ragged(args):
     xs, ys = workloads.ragged_pairs()
     X = RaggedPaths.from_list(xs, "cuda")
     Y = RaggedPaths.from_list(ys, "cuda")
+    tune = None if args.no_autotune else sk.autotune("pair", X, Y, lam)[0]
     out = torch.empty(len(xs), dtype=torch.float32, device="cuda")
     ws = torch.empty(sk.workspace_bytes(0, X, Y, lam, 0), dtype=torch.uint8, device="cuda")
 
-    def step():
+    def call():
         sk.sigkernel_pair(X, Y, lam, out=out, workspace=ws)
 
+    graph = None
+    if not args.eager:
+        graph, out = sk.capture_pair(X, Y, lam)
+    step, launch = (call, "eager") if graph is None else (graph.replay, "hipGraph replay")
     per, wall = time_steps(step, args.steps, args.warmup)
     ms = wall * 1e3 / args.steps
     cells = sum(((len(a) - 1) << lam) * ((len(b) - 1) << lam) for a, b in zip(xs, ys))
@@ -165,12 +192,12 @@ def bench_ragged(args):
         "config": {"workload": "4096 independent pairs, lengths U[64,1024], d=16, dyadic order 2",
                    "fine_cells": cells},
         "pairs_per_s": len(xs) / (ms / 1e3),
-        "avg_event_ms": float(np.mean(per)),
+        "avg_event_ms": float(np.mean(per)), "launch": launch, "tuning": tune,
     }
     if not args.no_cpu_baseline:
         import oracle
         rng = np.random.default_rng(1)
-        idx = rng.choice(len(xs), size=args.cpu_sample_pairs or 256, replace=False)
+        idx = rng.choice(len(xs), size=args.cpu_sample_pairs or len(xs), replace=False)
         sx = [xs[i].astype(np.float64) for i in idx]
         sy = [ys[i].astype(np.float64) for i in idx]
         t0 = time.perf_counter()
@@ -180,7 +207,8 @@ def bench_ragged(args):
         got = out.cpu().numpy()[idx]
         rec["cpu_baseline"] = {
             "value": scells / dt, "unit": "cells/s", "cores": oracle.max_threads(),
-            "kind": "oracle", "sample": f"{len(idx)} seeded pairs of the 4096, {dt:.2f} s",
+            "kind": "oracle", "sample": f"{len(idx)} of the 4096 pairs, all host threads, "
+                                        f"{dt:.2f} s",
             "gpu_max_err_on_sample": float(np.max(np.abs(got - ref) / np.maximum(1, np.abs(ref))))}
     print(json.dumps(rec), flush=True)
 
@@ -243,28 +271,20 @@ def main():
     dev = torch.device("cuda:0")
     Xt = torch.from_numpy(X).to(dev)
     Yt = torch.from_numpy(Y).to(dev)
+    # launch tuning is set-up: timed candidates run before the warm-up
+    tune = None if args.no_autotune else sk.autotune("gram", Xt, Yt, lam)[0]
     out = torch.empty((nx, ny), dtype=torch.float32, device=dev)
     ws = torch.empty(sk.workspace_bytes(1, Xt, Yt, lam, 0), dtype=torch.uint8, device=dev)
 
-    def step():
+    def call():
         sk.sigkernel_gram(Xt, Yt, lam, out=out, workspace=ws)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream(dev)
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        starts[i].record(stream)
-        step()
-        ends[i].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    per_launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    graph = None
+    if not args.eager:
+        graph, out = sk.capture_gram(Xt, Yt, lam)
+    step, launch = (call, "eager") if graph is None else (graph.replay, "hipGraph replay")
+    # HIP events on the stream the step is launched on (torch's current stream)
+    per_launch_ms, wall = time_steps(step, args.steps, args.warmup)
     ms_per_step = wall * 1e3 / args.steps
 
     M, N = (L - 1) << lam, (L - 1) << lam
@@ -292,6 +312,8 @@ def main():
                    "pairs": nx * ny, "fine_cells_per_pair": M * N, "sweep_state": "f64",
                    "increment_gram": "f32"},
         "pairs_per_s": pairs_per_s,
+        "launch": launch,
+        "tuning": tune,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
@@ -299,13 +321,13 @@ def main():
             "unit": "Tops/s",
             "frac": achieved / VALU_PEAK_TOPS,
             "traffic": None,
-            "kernel": "sweep_kernel (per-call events: increments + sweep)",
+            "kernel": "sweep_kernel (events around each step: increments + sweep)",
             "avg_launch_ms": avg_launch_s * 1e3,
             "ops_per_cell": sweep_ops_per_cell(d, lam),
         },
     }
     if not args.no_cpu_baseline:
-        n_sample = args.cpu_sample_pairs or 4096
+        n_sample = args.cpu_sample_pairs
         rec["cpu_baseline"] = cpu_baseline(X, Y, lam, n_sample, out.cpu().numpy())
     print(json.dumps(rec), flush=True)
 

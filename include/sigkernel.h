@@ -50,7 +50,9 @@ enum {
     SK_ERR_WORKSPACE = -4,   /* workspace NULL or smaller than required             */
     SK_ERR_FLAGS = -5,       /* unknown or incompatible flag bits                   */
     SK_ERR_HIP = -6,         /* a HIP launch failed                                 */
-    SK_ERR_UNSUPPORTED = -7  /* shape outside the compiled kernel configurations    */
+    SK_ERR_UNSUPPORTED = -7, /* shape outside the compiled kernel configurations    */
+    SK_ERR_STATE = -8        /* not allowed in the stream's current state (a call
+                                that synchronises, issued under graph capture)      */
 };
 
 /*
@@ -169,6 +171,98 @@ sk_status sigkernel_mmd2(const sk_paths *X, const sk_paths *Y, int32_t dyadic_or
 enum { SK_OP_PAIR = 0, SK_OP_GRAM = 1, SK_OP_GRAM_BACKWARD = 2, SK_OP_MMD2 = 3 };
 size_t sigkernel_workspace_bytes(int32_t op, const sk_paths *X, const sk_paths *Y,
                                  int32_t dyadic_order, uint32_t flags);
+
+/*
+ * Launch tuning (batching of pairs onto waves; no effect on any result).
+ *
+ * The Gram and pair calls map pairs onto one-wave sweeps.  Three launch
+ * parameters change only how that work is spread over the chip, never the
+ * arithmetic of a pair, so the forward outputs are bit-identical under every
+ * tuning (a Gram backward sums its per-pair gradients in an order that
+ * follows `run`: float32 rounding differences only):
+ *  - run: pairs (a, b), (a, b+1), ... streamed back to back through one wave
+ *    in a uniform Gram (the next pair's columns follow the previous pair's
+ *    without draining the wavefront);
+ *  - waves_per_block: one-wave sweeps per workgroup (1, 2 or 4);
+ *  - pair_blocks_per_cu: resident 4-wave workgroups per CU of the persistent
+ *    pair kernel (independent pairs, ragged batches, tall paths).
+ * A value of 0 keeps the built-in rule.  The library holds a table from
+ * problem keys to tunings; calls whose key is in the table use its entry.
+ * The workspace size of a Gram backward depends on `run`: query
+ * sigkernel_workspace_bytes after changing the table.  Table updates are
+ * serialised internally, but a call that runs while its entry changes may
+ * use either version: set the table before concurrent use.
+ */
+typedef struct sk_tune_key {
+    int32_t op;            /* SK_OP_PAIR, SK_OP_GRAM or SK_OP_GRAM_BACKWARD           */
+    int32_t dyadic_order;
+    int32_t symmetric;     /* 1 if SK_SYMMETRIC is set                                 */
+    int32_t ragged;        /* 1 if either batch has offsets                            */
+    int64_t nx, ny;        /* n_paths of X and Y                                       */
+    int32_t x_len, y_len;  /* len of X and Y (upper bounds when ragged)                */
+    int32_t dim;
+    int32_t reserved;      /* 0                                                        */
+} sk_tune_key;
+
+typedef struct sk_tune {
+    int32_t run;                 /* 1 .. 1024, 0 = built-in rule                       */
+    int32_t waves_per_block;     /* 1, 2 or 4, 0 = 4                                   */
+    int32_t pair_blocks_per_cu;  /* 1 .. 64, 0 = occupancy limit                       */
+    int32_t reserved;            /* 0                                                  */
+} sk_tune;
+
+/* The key of a call (op, batches, order and flags as the call receives them). */
+sk_status sigkernel_tune_key(int32_t op, const sk_paths *X, const sk_paths *Y,
+                             int32_t dyadic_order, uint32_t flags, sk_tune_key *key);
+/* Insert or replace the entry of `key`; tune == NULL removes it.  Out-of-range
+ * fields give SK_ERR_FLAGS (the table is then unchanged). */
+sk_status sigkernel_tune_set(const sk_tune_key *key, const sk_tune *tune);
+/* 1 and *tune filled if `key` has an entry, 0 if not, < 0 on a NULL argument. */
+int32_t sigkernel_tune_get(const sk_tune_key *key, sk_tune *tune);
+/* Copies up to `capacity` entries into keys / tunes (either may be NULL when
+ * capacity is 0) and returns the number of entries in the table. */
+int64_t sigkernel_tune_list(sk_tune_key *keys, sk_tune *tunes, int64_t capacity);
+void sigkernel_tune_clear(void);
+
+/*
+ * sigkernel_autotune -- time the candidate tunings of one forward call and
+ * keep the fastest in the table.
+ *   op: SK_OP_PAIR or SK_OP_GRAM, with the arguments that call takes (out is
+ *   its output: DEVICE float[n] or [nx * ny]; it is overwritten).
+ * Each candidate runs once untimed and then `reps` (>= 1) times between HIP
+ * events on `stream`; its time is the fastest repetition.  The call
+ * synchronises `stream` (SK_ERR_STATE under graph capture).  On success
+ * *best receives the chosen tuning, *best_ms (if not NULL) its time, and the
+ * table holds it under the call's key.  Candidates that the workspace cannot
+ * hold are skipped.
+ */
+sk_status sigkernel_autotune(int32_t op, const sk_paths *X, const sk_paths *Y,
+                             int32_t dyadic_order, uint32_t flags, float *out, void *ws,
+                             size_t ws_bytes, int32_t reps, void *stream, sk_tune *best,
+                             float *best_ms);
+
+/*
+ * HIP graphs of library calls (launch-bound loops: replay a whole call, or a
+ * sequence of calls, as one graph launch).
+ *   sigkernel_graph_begin(stream): start capturing `stream` (a created stream,
+ *   not the NULL stream; capture mode thread-local).  Library calls issued on
+ *   it until sigkernel_graph_end are recorded, not run.
+ *   sigkernel_graph_end(stream, &graph): stop capturing and instantiate.
+ *   SK_ERR_HIP if the capture was invalidated (a failed launch, a
+ *   synchronising call).
+ *   sigkernel_graph_launch(graph, stream): replay on any stream.
+ *   sigkernel_graph_destroy(graph).
+ * The library calls record only kernel launches (no memset or copy nodes),
+ * with every pointer and size fixed at capture: inputs, outputs and
+ * workspace must stay allocated while the graph lives, and a replay reads
+ * the inputs' contents at replay time.  Replays of one graph, or of graphs
+ * sharing a workspace, must not overlap.
+ */
+typedef struct sk_graph_s *sk_graph;
+sk_status sigkernel_graph_begin(void *stream);
+sk_status sigkernel_graph_end(void *stream, sk_graph *graph);
+sk_status sigkernel_graph_launch(sk_graph graph, void *stream);
+sk_status sigkernel_graph_destroy(sk_graph graph);
 
 /* Human-readable name of a status code (static storage). */
 const char *sigkernel_status_string(sk_status status);

@@ -21,6 +21,7 @@ SK_ERR_WORKSPACE = -4
 SK_ERR_FLAGS = -5
 SK_ERR_HIP = -6
 SK_ERR_UNSUPPORTED = -7
+SK_ERR_STATE = -8
 
 SK_SYMMETRIC = 1 << 0
 SK_NO_DIAG = 1 << 1
@@ -43,6 +44,16 @@ EXPORTED = (
     "sigkernel_workspace_bytes",
     "sigkernel_status_string",
     "sigkernel_version",
+    "sigkernel_tune_key",
+    "sigkernel_tune_set",
+    "sigkernel_tune_get",
+    "sigkernel_tune_list",
+    "sigkernel_tune_clear",
+    "sigkernel_autotune",
+    "sigkernel_graph_begin",
+    "sigkernel_graph_end",
+    "sigkernel_graph_launch",
+    "sigkernel_graph_destroy",
 )
 
 
@@ -53,6 +64,30 @@ class SkPaths(ctypes.Structure):
         ("n_paths", ctypes.c_int64),
         ("len", ctypes.c_int32),
         ("dim", ctypes.c_int32),
+    ]
+
+
+class SkTuneKey(ctypes.Structure):
+    _fields_ = [
+        ("op", ctypes.c_int32),
+        ("dyadic_order", ctypes.c_int32),
+        ("symmetric", ctypes.c_int32),
+        ("ragged", ctypes.c_int32),
+        ("nx", ctypes.c_int64),
+        ("ny", ctypes.c_int64),
+        ("x_len", ctypes.c_int32),
+        ("y_len", ctypes.c_int32),
+        ("dim", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class SkTune(ctypes.Structure):
+    _fields_ = [
+        ("run", ctypes.c_int32),
+        ("waves_per_block", ctypes.c_int32),
+        ("pair_blocks_per_cu", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -94,7 +129,33 @@ def load():
     lib.sigkernel_status_string.restype = ctypes.c_char_p
     lib.sigkernel_version.argtypes = []
     lib.sigkernel_version.restype = ctypes.c_char_p
+    K, T = ctypes.POINTER(SkTuneKey), ctypes.POINTER(SkTune)
+    lib.sigkernel_tune_key.argtypes = [i32, P, P, i32, u32, K]
+    lib.sigkernel_tune_key.restype = i32
+    lib.sigkernel_tune_set.argtypes = [K, T]
+    lib.sigkernel_tune_set.restype = i32
+    lib.sigkernel_tune_get.argtypes = [K, T]
+    lib.sigkernel_tune_get.restype = i32
+    lib.sigkernel_tune_list.argtypes = [K, T, ctypes.c_int64]
+    lib.sigkernel_tune_list.restype = ctypes.c_int64
+    lib.sigkernel_tune_clear.argtypes = []
+    lib.sigkernel_tune_clear.restype = None
+    lib.sigkernel_autotune.argtypes = [i32, P, P, i32, u32, vp, vp, sz, i32, vp, T,
+                                       ctypes.POINTER(ctypes.c_float)]
+    lib.sigkernel_autotune.restype = i32
+    lib.sigkernel_graph_begin.argtypes = [vp]
+    lib.sigkernel_graph_begin.restype = i32
+    lib.sigkernel_graph_end.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.sigkernel_graph_end.restype = i32
+    lib.sigkernel_graph_launch.argtypes = [vp, vp]
+    lib.sigkernel_graph_launch.restype = i32
+    lib.sigkernel_graph_destroy.argtypes = [vp]
+    lib.sigkernel_graph_destroy.restype = i32
     _lib = lib
+    cache = os.environ.get("SIGKERNEL_TUNE_CACHE")
+    if cache and os.path.exists(cache):
+        from .tuning import load_cache
+        load_cache(cache)
     return lib
 
 

@@ -7,6 +7,7 @@
 
 #include "../../include/sigkernel.h"
 #include "internal.h"
+#include "tune.h"
 
 namespace {
 
@@ -67,14 +68,11 @@ ForwardLayout forward_layout(const sk_paths* X, const sk_paths* Y) {
 
 size_t forward_ws(const sk_paths* X, const sk_paths* Y) { return forward_layout(X, Y).total; }
 
-// Pairs streamed through one wave for a Gram with a uniform y batch: enough
-// waves to fill every SIMD about four times, at most 64 pairs per run.
-int64_t choose_run(int64_t nx, int64_t ny) {
-  const char* env = getenv("SIGKERNEL_GRAM_RUN");
-  if (env) {
-    const long v = strtol(env, nullptr, 10);
-    if (v >= 1 && v <= 1024) return v;
-  }
+// Pairs streamed through one wave for a Gram with a uniform y batch: the
+// tuned value, else enough waves to fill every SIMD about four times, at
+// most 64 pairs per run.
+int64_t choose_run(int64_t nx, int64_t ny, int32_t tuned) {
+  if (tuned > 0) return tuned < ny ? tuned : (ny > 0 ? ny : 1);
   const int64_t target_waves = 256 * 4 * 4;
   int64_t run = (nx * ny) / target_waves;
   if (run < 1) run = 1;
@@ -129,7 +127,7 @@ PairLayout pair_layout(const sk_paths* X, const sk_paths* Y, int32_t lam, bool g
 constexpr size_t kStoreCapBytes = size_t(4) << 30;
 
 struct BackwardPlan {
-  int R;
+  int R, waves_per_block;
   int64_t run, runs_per_row, n_waves;
   int64_t store_stride;  // floats per wave
   int64_t chunk;         // waves per chunk
@@ -145,7 +143,9 @@ BackwardPlan backward_plan(const sk_paths* X, const sk_paths* Y, int32_t lam, ui
     P.total = forward_ws(X, Y);
     return P;
   }
-  P.run = choose_run(X->n_paths, Y->n_paths);
+  const sk_tune t = sk::tuning_for(SK_OP_GRAM_BACKWARD, X, Y, lam, flags);
+  P.waves_per_block = t.waves_per_block;
+  P.run = choose_run(X->n_paths, Y->n_paths, t.run);
   P.runs_per_row = (Y->n_paths + P.run - 1) / P.run;
   P.n_waves = X->n_paths * P.runs_per_row;
   const int64_t rs = (int64_t)P.R << lam;
@@ -163,7 +163,6 @@ BackwardPlan backward_plan(const sk_paths* X, const sk_paths* Y, int32_t lam, ui
   off += align256((size_t)X->n_paths * Y->n_paths * (size_t)(n > 0 ? n : 0) * X->dim *
                   sizeof(float));
   P.total = off;
-  (void)flags;
   return P;
 }
 
@@ -184,7 +183,8 @@ sk_status check_flags(uint32_t flags, uint32_t allowed) {
 
 // gram: every (a, b) of the two batches, out[a * ny + b]; else pairs (x_k, y_k)
 sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* out, void* ws,
-                    size_t ws_bytes, hipStream_t stream, bool gram, int rounding) {
+                    size_t ws_bytes, hipStream_t stream, bool gram, int rounding,
+                    const sk_tune& tune) {
   const int d = X->dim;
   const int dp = sk::padded_dim(d);
   const PairLayout PL = pair_layout(X, Y, lam, gram);
@@ -244,7 +244,8 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* ou
   a.order = order;
   a.count = counts;
   a.counter = counts + 2;
-  hipError_t e = sk::launch_pairs(a, lam, PL.rows_hi, d, PL.slots, stream);
+  hipError_t e =
+      sk::launch_pairs(a, lam, PL.rows_hi, d, PL.slots, stream, tune.pair_blocks_per_cu);
   if (e == hipSuccess) {
     // the short class follows the long one in `order`; its offset (the long
     // class's count) is only known on the device, where the kernel reads it
@@ -252,7 +253,7 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* ou
     a.count = counts + 1;
     a.counter = counts + 3;
     a.order_base = counts;  // start of the short class: order[counts[0]]
-    e = sk::launch_pairs(a, lam, PL.rows_lo, d, PL.slots, stream);
+    e = sk::launch_pairs(a, lam, PL.rows_lo, d, PL.slots, stream, tune.pair_blocks_per_cu);
   }
   if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;
   return e == hipSuccess ? SK_OK : SK_ERR_HIP;
@@ -261,7 +262,8 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* ou
 sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t flags,
                       float* out, void* ws, size_t ws_bytes, hipStream_t stream, int mode) {
   const int rounding = rounding_of(flags);
-  if (mode == 0) return run_pairs(X, Y, lam, out, ws, ws_bytes, stream, false, rounding);
+  const sk_tune tune = sk::tuning_for(mode == 0 ? SK_OP_PAIR : SK_OP_GRAM, X, Y, lam, flags);
+  if (mode == 0) return run_pairs(X, Y, lam, out, ws, ws_bytes, stream, false, rounding, tune);
   const int d = X->dim;
   const int dp = sk::padded_dim(d);
   const int64_t fine_rows = (int64_t)(X->len - 1) << lam;
@@ -270,7 +272,7 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_
     // x paths taller than one wave's strips: every (a, b) through the
     // persistent pair kernel with row bands (a symmetric Gram is filled in
     // both halves by solving both)
-    const sk_status st = run_pairs(X, Y, lam, out, ws, ws_bytes, stream, true, rounding);
+    const sk_status st = run_pairs(X, Y, lam, out, ws, ws_bytes, stream, true, rounding, tune);
     if (st == SK_OK && mode == 2 && (flags & SK_NO_DIAG) &&
         sk::launch_zero_diag(out, X->n_paths, stream) != hipSuccess)
       return SK_ERR_HIP;
@@ -318,11 +320,11 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_
     a.runs_per_row = 1;
     a.n_waves = X->n_paths;
   } else {
-    a.run = Y->offsets ? 1 : (int32_t)choose_run(X->n_paths, Y->n_paths);
+    a.run = Y->offsets ? 1 : (int32_t)choose_run(X->n_paths, Y->n_paths, tune.run);
     a.runs_per_row = (Y->n_paths + a.run - 1) / a.run;
     a.n_waves = X->n_paths * a.runs_per_row;
   }
-  const hipError_t e = sk::launch_sweep(a, lam, R, d, stream);
+  const hipError_t e = sk::launch_sweep(a, lam, R, d, stream, tune.waves_per_block);
   if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;
   return e == hipSuccess ? SK_OK : SK_ERR_HIP;
 }
@@ -382,6 +384,7 @@ const char* sigkernel_status_string(sk_status s) {
     case SK_ERR_FLAGS: return "invalid flags";
     case SK_ERR_HIP: return "HIP launch error";
     case SK_ERR_UNSUPPORTED: return "shape outside the compiled configurations";
+    case SK_ERR_STATE: return "not allowed while the stream is being captured";
     default: return "unknown status";
   }
 }
@@ -608,10 +611,12 @@ sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t 
     const int64_t nw = (P.n_waves - w0) < P.chunk ? (P.n_waves - w0) : P.chunk;
     fa.wave0 = w0;
     fa.n_waves = nw;
-    if (sk::launch_sweep_store(fa, lam, P.R, d, st) != hipSuccess) return SK_ERR_HIP;
+    if (sk::launch_sweep_store(fa, lam, P.R, d, st, P.waves_per_block) != hipSuccess)
+      return SK_ERR_HIP;
     ba.wave0 = w0;
     ba.n_waves = nw;
-    if (sk::launch_adjoint(ba, lam, P.R, d, st) != hipSuccess) return SK_ERR_HIP;
+    if (sk::launch_adjoint(ba, lam, P.R, d, st, P.waves_per_block) != hipSuccess)
+      return SK_ERR_HIP;
   }
   if (dX) {
     if (sk::launch_point_grad(part_x, P.runs_per_row, scale, sym ? part_y : nullptr, X->n_paths,

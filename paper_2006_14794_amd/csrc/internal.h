@@ -81,10 +81,11 @@ constexpr int kMaxRowsPerLane = 32;
 int choose_rows_per_lane(int64_t fine_rows, int lam, int dim);
 
 // Returns hipErrorInvalidValue when no compiled configuration covers the shape.
+// waves_per_block: 1, 2 or 4 one-wave sweeps per workgroup (0: 4).
 hipError_t launch_sweep(const SweepArgs& a, int lam, int rows_per_lane, int dim,
-                        hipStream_t stream);
+                        hipStream_t stream, int waves_per_block = 0);
 hipError_t launch_sweep_store(const SweepArgs& a, int lam, int rows_per_lane, int dim,
-                              hipStream_t stream);
+                              hipStream_t stream, int waves_per_block = 0);
 
 // Adjoint sweep of a Gram batch (uniform batches).
 struct BwdArgs {
@@ -105,7 +106,7 @@ struct BwdArgs {
 };
 
 hipError_t launch_adjoint(const BwdArgs& a, int lam, int rows_per_lane, int dim,
-                          hipStream_t stream);
+                          hipStream_t stream, int waves_per_block = 0);
 bool adjoint_supported(int rows_per_lane, int lam, int dim);
 hipError_t launch_point_grad(const float* part_x, int64_t runs_per_row, float scale,
                              const float* part_y, int64_t part_y_rows, int64_t part_y_ld,
@@ -150,9 +151,11 @@ struct PairPlanArgs {
 };
 
 hipError_t launch_pair_plan(const PairPlanArgs& p, hipStream_t stream);
-// Persistent launch: min(max_waves, resident waves) wavefronts.
+// Persistent launch: min(max_waves, blocks_per_cu 4-wave workgroups per CU)
+// wavefronts; blocks_per_cu 0 takes the occupancy limit.  Waves never wait on
+// one another, so any count is correct; it only changes the balance.
 hipError_t launch_pairs(const PairArgs& a, int lam, int rows_per_lane, int dim,
-                        int64_t max_waves, hipStream_t stream);
+                        int64_t max_waves, hipStream_t stream, int blocks_per_cu = 0);
 
 // Increment Gram of uniform batches on the matrix cores (gram_mfma.hip).
 struct GramArgs {

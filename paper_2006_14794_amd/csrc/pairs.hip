@@ -114,7 +114,7 @@ hipError_t launch_pair_plan(const PairPlanArgs& p, hipStream_t stream) {
 }
 
 hipError_t launch_pairs(const PairArgs& a, int lam, int R, int d, int64_t max_waves,
-                        hipStream_t stream) {
+                        hipStream_t stream, int blocks_per_cu_wanted) {
   auto f = reinterpret_cast<void (*)(const PairArgs)>(sweep_fn(kKernelPair, lam, R, d));
   if (!f) return hipErrorInvalidValue;
   int dev = 0, cus = 0, blocks_per_cu = 0;
@@ -124,6 +124,7 @@ hipError_t launch_pairs(const PairArgs& a, int lam, int R, int d, int64_t max_wa
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, f, 256, 0) != hipSuccess)
     return hipErrorInvalidValue;
   if (blocks_per_cu < 1) blocks_per_cu = 1;
+  if (blocks_per_cu_wanted > 0) blocks_per_cu = blocks_per_cu_wanted < 64 ? blocks_per_cu_wanted : 64;
   int64_t waves = (int64_t)cus * blocks_per_cu * 4;
   if (waves > max_waves) waves = max_waves;  // max_waves: a multiple of 4 (wave slots)
   const int64_t blocks = waves / 4 > 0 ? waves / 4 : 1;

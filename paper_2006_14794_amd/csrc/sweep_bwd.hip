@@ -40,13 +40,14 @@ __global__ __launch_bounds__(256) void point_grad_kernel(
 
 }  // namespace
 
-hipError_t launch_adjoint(const BwdArgs& a, int lam, int R, int d, hipStream_t stream) {
+hipError_t launch_adjoint(const BwdArgs& a, int lam, int R, int d, hipStream_t stream,
+                          int wpb) {
   auto f = reinterpret_cast<void (*)(const BwdArgs)>(sweep_fn(kKernelAdjoint, lam, R, d));
   if (!f) return hipErrorInvalidValue;
   if (a.n_waves == 0) return hipSuccess;
-  constexpr int kWavesPerBlock = 4;
-  const int64_t blocks = (a.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, stream, a);
+  if (wpb != 1 && wpb != 2) wpb = 4;  // the kernel is bounded to 256 threads
+  const int64_t blocks = (a.n_waves + wpb - 1) / wpb;
+  hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(64 * wpb), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -32,23 +32,25 @@ int choose_rows_per_lane(int64_t fine_rows, int lam, int d) {
 
 namespace {
 hipError_t launch_forward(int kind, const SweepArgs& a, int lam, int R, int d,
-                          hipStream_t stream) {
+                          hipStream_t stream, int wpb) {
   auto f = reinterpret_cast<void (*)(const SweepArgs)>(sweep_fn(kind, lam, R, d));
   if (!f) return hipErrorInvalidValue;
   if (a.n_waves == 0) return hipSuccess;
-  constexpr int kWavesPerBlock = 4;
-  const int64_t blocks = (a.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, stream, a);
+  if (wpb != 1 && wpb != 2) wpb = 4;  // the kernels are bounded to 256 threads
+  const int64_t blocks = (a.n_waves + wpb - 1) / wpb;
+  hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(64 * wpb), 0, stream, a);
   return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_sweep(const SweepArgs& a, int lam, int R, int d, hipStream_t stream) {
-  return launch_forward(kKernelForward, a, lam, R, d, stream);
+hipError_t launch_sweep(const SweepArgs& a, int lam, int R, int d, hipStream_t stream,
+                        int waves_per_block) {
+  return launch_forward(kKernelForward, a, lam, R, d, stream, waves_per_block);
 }
 
-hipError_t launch_sweep_store(const SweepArgs& a, int lam, int R, int d, hipStream_t stream) {
-  return launch_forward(kKernelForwardStore, a, lam, R, d, stream);
+hipError_t launch_sweep_store(const SweepArgs& a, int lam, int R, int d, hipStream_t stream,
+                              int waves_per_block) {
+  return launch_forward(kKernelForwardStore, a, lam, R, d, stream, waves_per_block);
 }
 
 }  // namespace sk

@@ -40,7 +40,7 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 
 def test_status_strings():
-    for code in range(-7, 1):
+    for code in range(-8, 1):
         s = sk.status_string(code)
         assert isinstance(s, str) and s
     assert sk.status_string(123) == "unknown status"
