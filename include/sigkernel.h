@@ -168,7 +168,11 @@ sk_status sigkernel_mmd2(const sk_paths *X, const sk_paths *Y, int32_t dyadic_or
                          void *stream);
 
 /* Workspace sizing.  op is one of the SK_OP_* values. */
-enum { SK_OP_PAIR = 0, SK_OP_GRAM = 1, SK_OP_GRAM_BACKWARD = 2, SK_OP_MMD2 = 3 };
+enum { SK_OP_PAIR = 0, SK_OP_GRAM = 1, SK_OP_GRAM_BACKWARD = 2, SK_OP_MMD2 = 3,
+       SK_OP_CORRECTOR_FEATURES = 4,  /* X, Y: the pairs                              */
+       SK_OP_CORRECTOR_BACKWARD = 5,  /* X->n_paths: the batch size (Y unused)        */
+       SK_OP_CORRECTOR_PREDICT = 6    /* X, Y: the pairs; dyadic_order: the fallback  */
+};
 size_t sigkernel_workspace_bytes(int32_t op, const sk_paths *X, const sk_paths *Y,
                                  int32_t dyadic_order, uint32_t flags);
 
@@ -263,6 +267,96 @@ sk_status sigkernel_graph_begin(void *stream);
 sk_status sigkernel_graph_end(void *stream, sk_graph *graph);
 sk_status sigkernel_graph_launch(sk_graph graph, void *stream);
 sk_status sigkernel_graph_destroy(sk_graph graph);
+
+/*
+ * Learned corrector (this library's extension; the paper has no learned
+ * component).  For pairs (x_k, y_k) of two uniform batches with at most 257
+ * points and 16 channels, a small convolutional network reads the
+ * dyadic-order-0 solve of the explicit scheme (Section 3.1, eq.
+ * (explicit_finite_diff) with lambda = 0) and predicts the order-3 terminal
+ * value and the size of its own error; pairs whose predicted error is too
+ * large are solved by the plain scheme at the fallback order instead, which
+ * is also what the network is trained against.
+ *
+ * Features: the order-0 grid of pair k has (m+1) x (n+1) nodes K and coarse
+ * coefficients c[p][q] = <x_{p+1} - x_p, y_{q+1} - y_q>.  Every 4 x 4 block
+ * (P, Q) of cells (64 x 64 blocks, NHWC) gets eight channels: the sums over its
+ * cells of c, c^2 (A + B) / 2, c (A + B), C - 1, c^2 C, c (B - A) (C = K[p][q],
+ * A = K[p+1][q], B = K[p][q+1]), then P / 63 and Q / 63; cells and blocks
+ * outside the grid contribute 0.  With norm != NULL each channel is
+ * normalised as (v - norm[c]) * norm[8 + c].
+ *
+ * Network: four layers of 3 x 3 convolution, stride 2, zero padding 1, 32
+ * output channels, bias and ReLU (64 -> 32 -> 16 -> 8 -> 4 blocks a side),
+ * weights and input activations rounded to bfloat16 (nearest even) before the
+ * products, float32 accumulation; then a dense head 512 -> 2 in float32 over
+ * the [4][4][32] map in NHWC order.  Flat float32 parameter vector of
+ * sigkernel_corrector_param_count() entries: per layer weights
+ * [32][3][3][Cin] (Cin = 8, 32, 32, 32) then 32 biases, then the head
+ * [2][512] and 2 biases.  Output y = (y0, y1): with target_norm = (mu,
+ * sigma), the corrected value is k_hat = k0 + mu + sigma y0 and the predicted
+ * error sigma exp(y1).
+ *
+ * Every buffer is DEVICE memory owned by the caller; per-pair buffers are
+ * contiguous in pair order.
+ */
+int64_t sigkernel_corrector_param_count(void);
+/* float32 activations per pair kept by the forward for the backward */
+int64_t sigkernel_corrector_act_floats(void);
+
+/* feats: float[n][64][64][8]; k0: float[n] (the order-0 terminal values).
+ * Workspace: sigkernel_workspace_bytes(SK_OP_CORRECTOR_FEATURES, X, Y, 0, 0).
+ * SK_ERR_UNSUPPORTED beyond 257 points or 16 channels, or for ragged batches. */
+sk_status sigkernel_corrector_features(const sk_paths *X, const sk_paths *Y, const float *norm,
+                                       float *feats, float *k0, void *ws, size_t ws_bytes,
+                                       void *stream);
+/* y: float[n][2]; acts: float[n * sigkernel_corrector_act_floats()] (the four
+ * layer outputs, layer-major: all pairs of layer 1, then of layer 2, ...). */
+sk_status sigkernel_corrector_forward(const float *params, const float *feats, int64_t n,
+                                      float *acts, float *y, void *stream);
+/* grads (overwritten) = d sum(dy * y) / d params, through the bf16 roundings
+ * as identities; the sums over pairs and positions run in a fixed order
+ * (deterministic).  Workspace: sigkernel_workspace_bytes(
+ * SK_OP_CORRECTOR_BACKWARD, X with n_paths = n, X, 0, 0). */
+sk_status sigkernel_corrector_backward(const float *params, const float *feats, const float *acts,
+                                       const float *dy, int64_t n, float *grads, void *ws,
+                                       size_t ws_bytes, void *stream);
+/* Training loss over n >= 1 pairs with targets t = (k_target - k0 - mu) / sigma:
+ *   loss = mean(r^2 + r^2 exp(-2 y1) / 2 + y1),  r = y0 - t,
+ * the second term's residual held constant for the gradient (a Gaussian
+ * likelihood of the residual, which teaches y1 the error size).
+ * loss: float[1]; dy: float[n][2] = d loss / d y. */
+sk_status sigkernel_corrector_loss(const float *y, const float *k_target, const float *k0,
+                                   const float *target_norm, int64_t n, float *loss, float *dy,
+                                   void *stream);
+/* Adam with bias correction; *step (DEVICE int32) is incremented first and
+ * the update uses the new value t: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+sk_status sigkernel_adam_step(float *params, const float *grads, float *m, float *v, int64_t n,
+                              int32_t *step, float lr, float beta1, float beta2, float eps,
+                              void *stream);
+/* Per-channel mean and 1 / (population) standard deviation of v = x - sub
+ * (sub nullable: v = x), both [rows][channels] (channels <= 8; a constant
+ * channel gets 1), summed in a fixed order in double (the normalisation
+ * constants of the features and of the training targets).
+ * ws: SK_CHANNEL_STATS_WORKSPACE_BYTES. */
+#define SK_CHANNEL_STATS_WORKSPACE_BYTES 32832
+sk_status sigkernel_channel_stats(const float *x, const float *sub, int64_t rows,
+                                  int32_t channels, float *mean, float *rstd, void *ws,
+                                  size_t ws_bytes, void *stream);
+/* Corrected order-3 values of the pairs: features, network, then
+ *   k_hat = k0 + mu + sigma y0,  e = sigma exp(y1);
+ * a pair falls back when kappa e > tol max(1, |k_hat|) and then receives the
+ * plain scheme at `fallback_order` (out), computed on the device for exactly
+ * those pairs (no host synchronisation).  out: float[n]; err (nullable):
+ * float[n] predicted errors; fallback (nullable): int32[n], 1 where the plain
+ * solve was used.  Workspace: sigkernel_workspace_bytes(
+ * SK_OP_CORRECTOR_PREDICT, X, Y, fallback_order, 0). */
+sk_status sigkernel_corrector_predict(const sk_paths *X, const sk_paths *Y, int32_t fallback_order,
+                                      const float *params, const float *norm,
+                                      const float *target_norm, float kappa, float tol, float *out,
+                                      float *err, int32_t *fallback, void *ws, size_t ws_bytes,
+                                      void *stream);
 
 /* Human-readable name of a status code (static storage). */
 const char *sigkernel_status_string(sk_status status);

@@ -12,6 +12,8 @@ from .api import (RaggedPaths, SigKernelGram, SigKernelGramSymmetric, SigKernelM
                   sigkernel_gram, sigkernel_gram_backward, sigkernel_increment_gram, sigkernel_mmd2,
                   sigkernel_pair,
                   workspace_bytes)
+from . import corrector
+from .corrector import Corrector
 from .graph import CapturedCalls, capture_gram, capture_mmd2, capture_pair
 from .tuning import autotune, load_cache, save_cache, tune_clear, tune_get, tune_key, tune_list, tune_set
 
@@ -21,6 +23,7 @@ __all__ = [
     "sigkernel_gram", "sigkernel_gram_backward", "sigkernel_pair",
     "status_string", "version", "workspace_bytes",
     "SK_SYMMETRIC", "SK_NO_DIAG",
+    "Corrector", "corrector",
     "CapturedCalls", "capture_gram", "capture_mmd2", "capture_pair",
     "autotune", "load_cache", "save_cache", "tune_clear", "tune_get", "tune_key", "tune_list",
     "tune_set",

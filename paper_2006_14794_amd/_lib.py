@@ -33,6 +33,10 @@ SK_OP_PAIR = 0
 SK_OP_GRAM = 1
 SK_OP_GRAM_BACKWARD = 2
 SK_OP_MMD2 = 3
+SK_OP_CORRECTOR_FEATURES = 4
+SK_OP_CORRECTOR_BACKWARD = 5
+SK_OP_CORRECTOR_PREDICT = 6
+SK_CHANNEL_STATS_WORKSPACE_BYTES = 32832
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTED = (
@@ -54,6 +58,15 @@ EXPORTED = (
     "sigkernel_graph_end",
     "sigkernel_graph_launch",
     "sigkernel_graph_destroy",
+    "sigkernel_corrector_param_count",
+    "sigkernel_corrector_act_floats",
+    "sigkernel_corrector_features",
+    "sigkernel_corrector_forward",
+    "sigkernel_corrector_backward",
+    "sigkernel_corrector_loss",
+    "sigkernel_adam_step",
+    "sigkernel_channel_stats",
+    "sigkernel_corrector_predict",
 )
 
 
@@ -151,6 +164,26 @@ def load():
     lib.sigkernel_graph_launch.restype = i32
     lib.sigkernel_graph_destroy.argtypes = [vp]
     lib.sigkernel_graph_destroy.restype = i32
+    i64, f32 = ctypes.c_int64, ctypes.c_float
+    lib.sigkernel_corrector_param_count.argtypes = []
+    lib.sigkernel_corrector_param_count.restype = i64
+    lib.sigkernel_corrector_act_floats.argtypes = []
+    lib.sigkernel_corrector_act_floats.restype = i64
+    lib.sigkernel_corrector_features.argtypes = [P, P, vp, vp, vp, vp, sz, vp]
+    lib.sigkernel_corrector_features.restype = i32
+    lib.sigkernel_corrector_forward.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.sigkernel_corrector_forward.restype = i32
+    lib.sigkernel_corrector_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, sz, vp]
+    lib.sigkernel_corrector_backward.restype = i32
+    lib.sigkernel_corrector_loss.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
+    lib.sigkernel_corrector_loss.restype = i32
+    lib.sigkernel_adam_step.argtypes = [vp, vp, vp, vp, i64, vp, f32, f32, f32, f32, vp]
+    lib.sigkernel_adam_step.restype = i32
+    lib.sigkernel_channel_stats.argtypes = [vp, vp, i64, i32, vp, vp, vp, sz, vp]
+    lib.sigkernel_channel_stats.restype = i32
+    lib.sigkernel_corrector_predict.argtypes = [P, P, i32, vp, vp, vp, f32, f32, vp, vp, vp, vp,
+                                                sz, vp]
+    lib.sigkernel_corrector_predict.restype = i32
     _lib = lib
     cache = os.environ.get("SIGKERNEL_TUNE_CACHE")
     if cache and os.path.exists(cache):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include "../../include/sigkernel.h"
+#include "corrector.h"
 #include "internal.h"
 #include "tune.h"
 
@@ -368,6 +369,102 @@ Mmd2Layout mmd2_layout(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32
   return L;
 }
 
+// ---- learned corrector ----------------------------------------------------
+sk_status check_corrector_batches(const sk_paths* X, const sk_paths* Y) {
+  if (!X || !Y) return SK_ERR_NULL;
+  if (!valid_batch(X) || !valid_batch(Y)) return SK_ERR_SHAPE;
+  if (X->dim != Y->dim || X->n_paths != Y->n_paths) return SK_ERR_SHAPE;
+  if (X->offsets || Y->offsets) return SK_ERR_UNSUPPORTED;
+  // the feature map holds 64 x 64 blocks of 4 x 4 coarse cells
+  if (X->len > 257 || Y->len > 257 || X->dim > 16) return SK_ERR_UNSUPPORTED;
+  if (X->n_paths > 0 && (!X->points || !Y->points)) return SK_ERR_NULL;
+  return SK_OK;
+}
+
+struct DwPlan {
+  int nblocks;
+  int64_t per_block;
+};
+
+// weight-gradient partials of layer l: at most 256 workgroups, whole chunks
+// of 16 output positions each
+DwPlan dw_plan(int l, int64_t n) {
+  const int64_t ho = sk::corr::kLayerHi[l] / 2;
+  const int64_t T = n * ho * ho;
+  if (T == 0) return DwPlan{0, 16};
+  int64_t nb = (T + 63) / 64;
+  if (nb > 256) nb = 256;
+  int64_t per = (T + nb - 1) / nb;
+  per = (per + 15) & ~int64_t(15);
+  return DwPlan{(int)((T + per - 1) / per), per};
+}
+
+size_t corrector_bwd_ws(int64_t n) {
+  size_t part = 0;
+  for (int l = 0; l < sk::corr::kLayers; ++l) {
+    const size_t w = (size_t)sk::corr::layer_params(l) * sizeof(float);
+    const size_t v = (size_t)dw_plan(l, n).nblocks * w;
+    part = v > part ? v : part;
+  }
+  return 2 * align256((size_t)n * sk::corr::kFeatFloats * sizeof(float)) + align256(part) + 256;
+}
+
+struct PredictLayout {
+  PairLayout pl;
+  size_t feats, acts, y, k0, total;
+};
+
+PredictLayout predict_layout(const sk_paths* X, const sk_paths* Y, int32_t lam) {
+  PredictLayout L{};
+  L.pl = pair_layout(X, Y, lam, false);
+  const size_t n = (size_t)X->n_paths;
+  size_t off = L.pl.total;
+  L.feats = off;
+  off += align256(n * sk::corr::kFeatFloats * sizeof(float));
+  L.acts = off;
+  off += align256(n * (size_t)sk::corr::kActFloats * sizeof(float));
+  L.y = off;
+  off += align256(n * 2 * sizeof(float));
+  L.k0 = off;
+  off += align256(n * sizeof(float));
+  L.total = off;
+  return L;
+}
+
+// Dense unscaled increments of both batches of a corrector call.
+sk_status corrector_increments(const sk_paths* X, const sk_paths* Y, char* base, float** incx,
+                               float** incy, hipStream_t st) {
+  const int dp = sk::padded_dim(X->dim);
+  const ForwardLayout L = forward_layout(X, Y);
+  *incx = reinterpret_cast<float*>(base + L.incx) + sk::kStreamPad * dp;
+  *incy = reinterpret_cast<float*>(base + L.incy) + sk::kStreamPad * dp;
+  if (sk::launch_increments(to_batch(X), nullptr, 1.0f, dp, *incx, st) != hipSuccess)
+    return SK_ERR_HIP;
+  if (sk::launch_increments(to_batch(Y), nullptr, 1.0f, dp, *incy, st) != hipSuccess)
+    return SK_ERR_HIP;
+  return SK_OK;
+}
+
+sk_status corrector_forward(const float* params, const float* feats, int64_t n, float* acts,
+                            float* y, hipStream_t st) {
+  using namespace sk::corr;
+  const float* in = feats;
+  for (int l = 0; l < kLayers; ++l) {
+    ConvArgs a{};
+    a.in = in;
+    a.w = params + param_offset(l);
+    a.b = a.w + (int64_t)kCout * 9 * kLayerCin[l];
+    a.out = acts + act_offset(l) * n;
+    a.n = n;
+    if (launch_conv_fwd(l, a, st) != hipSuccess) return SK_ERR_HIP;
+    in = a.out;
+  }
+  if (launch_head_fwd(in, params + kHeadOffset, params + kHeadOffset + 2 * kHeadIn, n, y, st) !=
+      hipSuccess)
+    return SK_ERR_HIP;
+  return SK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -410,6 +507,14 @@ size_t sigkernel_workspace_bytes(int32_t op, const sk_paths* X, const sk_paths* 
     case SK_OP_MMD2:
       if (X->offsets || Y->offsets || X->dim != Y->dim) return 0;
       return mmd2_layout(X, Y, dyadic_order, flags).total;
+    case SK_OP_CORRECTOR_FEATURES:
+      if (check_corrector_batches(X, Y) == SK_ERR_SHAPE) return 0;
+      return forward_ws(X, Y);
+    case SK_OP_CORRECTOR_BACKWARD:
+      return corrector_bwd_ws(X->n_paths);
+    case SK_OP_CORRECTOR_PREDICT:
+      if (check_corrector_batches(X, Y) == SK_ERR_SHAPE) return 0;
+      return predict_layout(X, Y, dyadic_order).total;
     default:
       return 0;
   }
@@ -629,6 +734,187 @@ sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t 
       return SK_ERR_HIP;
   }
   return SK_OK;
+}
+
+// ---- learned corrector ----------------------------------------------------
+int64_t sigkernel_corrector_param_count(void) { return sk::corr::kParams; }
+int64_t sigkernel_corrector_act_floats(void) { return sk::corr::kActFloats; }
+
+sk_status sigkernel_corrector_features(const sk_paths* X, const sk_paths* Y, const float* norm,
+                                       float* feats, float* k0, void* ws, size_t ws_bytes,
+                                       void* stream) {
+  if (sk_status c = check_corrector_batches(X, Y)) return c;
+  if (X->n_paths == 0) return SK_OK;
+  if (!feats || !k0) return SK_ERR_NULL;
+  if (!ws || ws_bytes < forward_ws(X, Y)) return SK_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  sk::corr::FeatArgs fa{};
+  float *incx, *incy;
+  if (sk_status c = corrector_increments(X, Y, static_cast<char*>(ws), &incx, &incy, st)) return c;
+  fa.incx = incx;
+  fa.incy = incy;
+  fa.m = X->len - 1;
+  fa.n = Y->len - 1;
+  fa.npairs = X->n_paths;
+  fa.norm = norm;
+  fa.feats = feats;
+  fa.k0 = k0;
+  return sk::corr::launch_features(fa, X->dim, st) == hipSuccess ? SK_OK : SK_ERR_HIP;
+}
+
+sk_status sigkernel_corrector_forward(const float* params, const float* feats, int64_t n,
+                                      float* acts, float* y, void* stream) {
+  if (n < 0) return SK_ERR_SHAPE;
+  if (n == 0) return SK_OK;
+  if (!params || !feats || !acts || !y) return SK_ERR_NULL;
+  return corrector_forward(params, feats, n, acts, y, static_cast<hipStream_t>(stream));
+}
+
+sk_status sigkernel_corrector_backward(const float* params, const float* feats, const float* acts,
+                                       const float* dy, int64_t n, float* grads, void* ws,
+                                       size_t ws_bytes, void* stream) {
+  using namespace sk::corr;
+  if (n < 0) return SK_ERR_SHAPE;
+  if (!params || !grads || (n > 0 && (!feats || !acts || !dy))) return SK_ERR_NULL;
+  const size_t need = corrector_bwd_ws(n);
+  if (!ws || ws_bytes < need) return SK_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  const size_t act_bytes = align256((size_t)n * kFeatFloats * sizeof(float));
+  float* dA = reinterpret_cast<float*>(base);
+  float* dB = reinterpret_cast<float*>(base + act_bytes);
+  float* partial = reinterpret_cast<float*>(base + 2 * act_bytes);
+  if (launch_head_bwd(dy, acts + act_offset(3) * n, params + kHeadOffset, n, dA,
+                      grads + kHeadOffset, st) != hipSuccess)
+    return SK_ERR_HIP;
+  for (int l = kLayers - 1; l >= 0; --l) {
+    const DwPlan P = dw_plan(l, n);
+    ConvBwdArgs a{};
+    a.in = l == 0 ? feats : acts + act_offset(l - 1) * n;
+    a.w = params + param_offset(l);
+    a.out = acts + act_offset(l) * n;
+    a.dout = dA;
+    a.din = dB;
+    a.partial = partial;
+    a.n = n;
+    a.nblocks = P.nblocks;
+    a.per_block = P.per_block;
+    if (launch_conv_dw(l, a, grads + param_offset(l), st) != hipSuccess) return SK_ERR_HIP;
+    if (l > 0) {
+      if (launch_conv_dx(l, a, st) != hipSuccess) return SK_ERR_HIP;
+      float* t = dA;
+      dA = dB;
+      dB = t;
+    }
+  }
+  return SK_OK;
+}
+
+sk_status sigkernel_corrector_loss(const float* y, const float* k_target, const float* k0,
+                                   const float* target_norm, int64_t n, float* loss, float* dy,
+                                   void* stream) {
+  if (n < 1) return SK_ERR_SHAPE;
+  if (!y || !k_target || !k0 || !target_norm || !loss || !dy) return SK_ERR_NULL;
+  return sk::corr::launch_loss(y, k_target, k0, target_norm, n, loss, dy,
+                               static_cast<hipStream_t>(stream)) == hipSuccess
+             ? SK_OK
+             : SK_ERR_HIP;
+}
+
+sk_status sigkernel_adam_step(float* params, const float* grads, float* m, float* v, int64_t n,
+                              int32_t* step, float lr, float beta1, float beta2, float eps,
+                              void* stream) {
+  if (n < 0) return SK_ERR_SHAPE;
+  if (!step || (n > 0 && (!params || !grads || !m || !v))) return SK_ERR_NULL;
+  if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !(eps > 0.0f))
+    return SK_ERR_FLAGS;
+  return sk::corr::launch_adam(params, grads, m, v, n, step, lr, beta1, beta2, eps,
+                               static_cast<hipStream_t>(stream)) == hipSuccess
+             ? SK_OK
+             : SK_ERR_HIP;
+}
+
+sk_status sigkernel_channel_stats(const float* x, const float* sub, int64_t rows, int32_t channels,
+                                  float* mean, float* rstd, void* ws, size_t ws_bytes,
+                                  void* stream) {
+  if (rows < 1 || channels < 1 || channels > sk::corr::kMaxStatChannels) return SK_ERR_SHAPE;
+  if (!x || !mean || !rstd) return SK_ERR_NULL;
+  if (!ws || ws_bytes < sk::corr::kStatsWorkspaceBytes) return SK_ERR_WORKSPACE;
+  return sk::corr::launch_channel_stats(x, sub, rows, channels, mean, rstd,
+                                        static_cast<double*>(ws),
+                                        static_cast<hipStream_t>(stream)) == hipSuccess
+             ? SK_OK
+             : SK_ERR_HIP;
+}
+
+sk_status sigkernel_corrector_predict(const sk_paths* X, const sk_paths* Y, int32_t fallback_order,
+                                      const float* params, const float* norm,
+                                      const float* target_norm, float kappa, float tol, float* out,
+                                      float* err, int32_t* fallback, void* ws, size_t ws_bytes,
+                                      void* stream) {
+  if (sk_status c = check_corrector_batches(X, Y)) return c;
+  if (fallback_order < 0 || fallback_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (!(kappa >= 0.0f) || !(tol >= 0.0f)) return SK_ERR_FLAGS;
+  const int64_t n = X->n_paths;
+  if (n == 0) return SK_OK;
+  if (!params || !norm || !target_norm || !out) return SK_ERR_NULL;
+  if (n > INT32_MAX) return SK_ERR_UNSUPPORTED;
+  const PredictLayout L = predict_layout(X, Y, fallback_order);
+  if (L.pl.rows_hi == 0) return SK_ERR_UNSUPPORTED;
+  if (!ws || ws_bytes < L.total) return SK_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  float *incx, *incy;
+  if (sk_status c = corrector_increments(X, Y, base, &incx, &incy, st)) return c;
+  float* feats = reinterpret_cast<float*>(base + L.feats);
+  float* acts = reinterpret_cast<float*>(base + L.acts);
+  float* y = reinterpret_cast<float*>(base + L.y);
+  float* k0 = reinterpret_cast<float*>(base + L.k0);
+  sk::corr::FeatArgs fa{};
+  fa.incx = incx;
+  fa.incy = incy;
+  fa.m = X->len - 1;
+  fa.n = Y->len - 1;
+  fa.npairs = n;
+  fa.norm = norm;
+  fa.feats = feats;
+  fa.k0 = k0;
+  if (sk::corr::launch_features(fa, X->dim, st) != hipSuccess) return SK_ERR_HIP;
+  if (sk_status c = corrector_forward(params, feats, n, acts, y, st)) return c;
+  int32_t* order = reinterpret_cast<int32_t*>(base + L.pl.order);
+  int32_t* counts = reinterpret_cast<int32_t*>(base + L.pl.counts);
+  sk::corr::DecideArgs da{};
+  da.k0 = k0;
+  da.y = y;
+  da.tnorm = target_norm;
+  da.kappa = kappa;
+  da.tol = tol;
+  da.n = n;
+  da.out = out;
+  da.err = err;
+  da.fallback = fallback;
+  da.order = order;
+  da.count = counts;
+  if (sk::corr::launch_decide(da, st) != hipSuccess) return SK_ERR_HIP;
+  // the plain solve at the fallback order for the compacted pairs only: the
+  // persistent pair kernel reads their number from the device
+  sk::PairArgs a{};
+  a.incx = incx;
+  a.incy = incy;
+  a.x_len = X->len;
+  a.y_len = Y->len;
+  a.scale = ldexp(1.0, -(2 * fallback_order + 1));
+  a.order = order;
+  a.count = counts;
+  a.counter = counts + 2;
+  a.bandbuf = reinterpret_cast<double*>(base + L.pl.bands);
+  a.band_stride = L.pl.band_stride;
+  a.out = out;
+  const hipError_t e =
+      sk::launch_pairs(a, fallback_order, L.pl.rows_hi, X->dim, L.pl.slots, st, 0);
+  if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;
+  return e == hipSuccess ? SK_OK : SK_ERR_HIP;
 }
 
 }  // extern "C"
