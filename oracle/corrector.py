@@ -26,7 +26,10 @@ written out plainly:
   are exact here (FP64).  The backward is the chain rule through the rounded
   operands (the rounding itself is passed straight through);
 * ``network_forward`` / ``network_backward``: four such layers with ReLU
-  (32 channels each), then a dense head 512 -> 2 in plain arithmetic;
+  (32 channels each), then a dense head 512 -> 2 whose input activations are
+  rounded to bfloat16 like every layer's (its weights stay float32); the
+  network therefore only ever reads bfloat16 activations, and the features
+  it reads are ``bf16_round(normalise(block_features))``;
 * ``loss_and_grad``: squared error of output 0 against the normalised target,
   plus the Gaussian negative log-likelihood of that (detached) residual under
   the predicted log-scale output 1;
@@ -178,7 +181,7 @@ def network_forward(theta: np.ndarray, feats: np.ndarray, rounding: bool = True)
         pre = conv_forward(acts[-1], p[f"w{i + 1}"], p[f"b{i + 1}"], rounding)
         pres.append(pre)
         acts.append(np.maximum(pre, 0.0))
-    flat = acts[-1].reshape(acts[-1].shape[0], -1)
+    flat = _rnd(acts[-1].reshape(acts[-1].shape[0], -1), rounding)
     y = flat @ p["wh"].T + p["bh"]
     return y, (acts, pres, flat, rounding)
 

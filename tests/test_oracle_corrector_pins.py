@@ -105,7 +105,7 @@ def torch_network(theta, feats, rounding):
     for i in range(4):
         w = rnd(p[f"w{i + 1}"].permute(0, 3, 1, 2))
         a = torch.relu(torch.nn.functional.conv2d(rnd(a), w, p[f"b{i + 1}"], stride=2, padding=1))
-    flat = a.permute(0, 2, 3, 1).reshape(a.shape[0], -1)
+    flat = rnd(a.permute(0, 2, 3, 1).reshape(a.shape[0], -1))
     return flat @ p["wh"].T + p["bh"], p
 
 
