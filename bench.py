@@ -45,12 +45,14 @@ def parse():
                     help="keep the built-in launch rules instead of autotuning (untimed) first")
     ap.add_argument("--cpu-sample-pairs", type=int, default=0,
                     help="pairs of the workload timed on the CPU oracle (0: all)")
-    ap.add_argument("--workload", choices=["gram", "mmd", "ragged", "increment_gram"],
+    ap.add_argument("--workload", choices=["gram", "mmd", "ragged", "increment_gram", "corrector"],
                     default="gram",
                     help="gram: the 128 x 128 Gram batch (default, the reported metric); "
                          "mmd: unbiased MMD^2 of 64 vs 64 512-point paths with its gradient; "
                          "ragged: 4096 independent pairs of uneven lengths; "
-                         "increment_gram: the coarse Gram of the Gram batch on the matrix cores")
+                         "increment_gram: the coarse Gram of the Gram batch on the matrix cores; "
+                         "corrector: order-3 values of 65536 held-out pairs by the learned "
+                         "corrector with fallback, against the plain order-3 solve")
     return ap.parse_args()
 
 
@@ -244,6 +246,51 @@ def bench_increment_gram(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_corrector(args):
+    """65536 held-out pairs (256 points, R^8): the learned corrector (order-0
+    features, network, device-side fallback to the plain order-3 solve)
+    against the plain order-3 solve, both timed over whole batches."""
+    import torch
+    import paper_2006_14794_amd as sk
+    import workloads
+    from paper_2006_14794_amd import corrector as corr
+    n = 65536
+    X, Y = workloads.corrector_pairs(workloads.SEED_CORRECTOR_EVAL, n)
+    Xc, Yc = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    del X, Y
+    model = sk.Corrector.load(os.path.join(ROOT, "paper_2006_14794_amd", "corrector_weights.npz"))
+    plain = torch.empty(n, dtype=torch.float32, device="cuda")
+
+    def plain_step():
+        sk.sigkernel_pair(Xc, Yc, 3, out=plain)
+    res = {}
+
+    def learned_step():
+        res["out"] = model.predict(Xc, Yc, kappa=3.0, tol=1e-3, chunk=n)
+    per_p, wall_p = time_steps(plain_step, args.steps, args.warmup)
+    per_l, wall_l = time_steps(learned_step, args.steps, args.warmup)
+    ms_p = wall_p * 1e3 / args.steps
+    ms_l = wall_l * 1e3 / args.steps
+    out, err, fb = res["out"]
+    k3 = plain.cpu().numpy().astype(np.float64)
+    e = np.abs(out.cpu().numpy() - k3) / np.abs(k3)
+    cells3 = n * (255 << 3) ** 2
+    rec = {
+        "metric": "order-3-equivalent grid-cell updates/s, learned corrector with fallback",
+        "value": cells3 / (ms_l / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_l, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+bf16", "data": "synthetic",
+        "config": {"workload": "65536 held-out pairs, 256-point paths in R^8, std 0.3/16, "
+                               "order-0 input, order-3 target, kappa 3, tol 1e-3"},
+        "plain_order3": {"ms_per_step": ms_p, "cells_per_s": cells3 / (ms_p / 1e3)},
+        "speedup_vs_plain_order3": ms_p / ms_l,
+        "fallback_fraction": float(fb.float().mean().item()),
+        "rel_err_vs_order3": {"median": float(np.median(e)),
+                              "p99": float(np.percentile(e, 99)), "max": float(e.max())},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -258,6 +305,9 @@ def main():
         return
     if args.workload == "increment_gram":
         bench_increment_gram(args)
+        return
+    if args.workload == "corrector":
+        bench_corrector(args)
         return
 
     import torch

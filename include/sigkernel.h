@@ -297,30 +297,32 @@ sk_status sigkernel_graph_destroy(sk_graph graph);
  * sigma), the corrected value is k_hat = k0 + mu + sigma y0 and the predicted
  * error sigma exp(y1).
  *
+ * Features and activations are stored as bfloat16 (uint16_t bit patterns):
+ * every consumer reads them as bf16 anyway, so the storage loses nothing.
  * Every buffer is DEVICE memory owned by the caller; per-pair buffers are
  * contiguous in pair order.
  */
 int64_t sigkernel_corrector_param_count(void);
-/* float32 activations per pair kept by the forward for the backward */
-int64_t sigkernel_corrector_act_floats(void);
+/* bf16 activations per pair kept by the forward for the backward */
+int64_t sigkernel_corrector_act_elems(void);
 
-/* feats: float[n][64][64][8]; k0: float[n] (the order-0 terminal values).
+/* feats: bf16[n][64][64][8]; k0: float[n] (the order-0 terminal values).
  * Workspace: sigkernel_workspace_bytes(SK_OP_CORRECTOR_FEATURES, X, Y, 0, 0).
  * SK_ERR_UNSUPPORTED beyond 257 points or 16 channels, or for ragged batches. */
 sk_status sigkernel_corrector_features(const sk_paths *X, const sk_paths *Y, const float *norm,
-                                       float *feats, float *k0, void *ws, size_t ws_bytes,
+                                       uint16_t *feats, float *k0, void *ws, size_t ws_bytes,
                                        void *stream);
-/* y: float[n][2]; acts: float[n * sigkernel_corrector_act_floats()] (the four
+/* y: float[n][2]; acts: bf16[n * sigkernel_corrector_act_elems()] (the four
  * layer outputs, layer-major: all pairs of layer 1, then of layer 2, ...). */
-sk_status sigkernel_corrector_forward(const float *params, const float *feats, int64_t n,
-                                      float *acts, float *y, void *stream);
+sk_status sigkernel_corrector_forward(const float *params, const uint16_t *feats, int64_t n,
+                                      uint16_t *acts, float *y, void *stream);
 /* grads (overwritten) = d sum(dy * y) / d params, through the bf16 roundings
  * as identities; the sums over pairs and positions run in a fixed order
  * (deterministic).  Workspace: sigkernel_workspace_bytes(
  * SK_OP_CORRECTOR_BACKWARD, X with n_paths = n, X, 0, 0). */
-sk_status sigkernel_corrector_backward(const float *params, const float *feats, const float *acts,
-                                       const float *dy, int64_t n, float *grads, void *ws,
-                                       size_t ws_bytes, void *stream);
+sk_status sigkernel_corrector_backward(const float *params, const uint16_t *feats,
+                                       const uint16_t *acts, const float *dy, int64_t n,
+                                       float *grads, void *ws, size_t ws_bytes, void *stream);
 /* Training loss over n >= 1 pairs with targets t = (k_target - k0 - mu) / sigma:
  *   loss = mean(r^2 + r^2 exp(-2 y1) / 2 + y1),  r = y0 - t,
  * the second term's residual held constant for the gradient (a Gaussian
@@ -338,13 +340,15 @@ sk_status sigkernel_adam_step(float *params, const float *grads, float *m, float
 /* Per-channel mean and 1 / (population) standard deviation of v = x - sub
  * (sub nullable: v = x), both [rows][channels] (channels <= 8; a constant
  * channel gets 1), summed in a fixed order in double (the normalisation
- * constants of the features and of the training targets).
- * ws: SK_CHANNEL_STATS_WORKSPACE_BYTES. */
+ * constants of the features and of the training targets).  x_dtype: 0
+ * float32, 1 bf16 (sub is float32).  ws: SK_CHANNEL_STATS_WORKSPACE_BYTES. */
 #define SK_CHANNEL_STATS_WORKSPACE_BYTES 32832
-sk_status sigkernel_channel_stats(const float *x, const float *sub, int64_t rows,
+sk_status sigkernel_channel_stats(const void *x, int32_t x_dtype, const float *sub, int64_t rows,
                                   int32_t channels, float *mean, float *rstd, void *ws,
                                   size_t ws_bytes, void *stream);
-/* Corrected order-3 values of the pairs: features, network, then
+/* Corrected order-3 values of the pairs: features, then the whole network
+ * per pair on chip (one workgroup per pair, activations in LDS; the same
+ * arithmetic as sigkernel_corrector_forward, bit for bit), then
  *   k_hat = k0 + mu + sigma y0,  e = sigma exp(y1);
  * a pair falls back when kappa e > tol max(1, |k_hat|) and then receives the
  * plain scheme at `fallback_order` (out), computed on the device for exactly

@@ -59,7 +59,7 @@ EXPORTED = (
     "sigkernel_graph_launch",
     "sigkernel_graph_destroy",
     "sigkernel_corrector_param_count",
-    "sigkernel_corrector_act_floats",
+    "sigkernel_corrector_act_elems",
     "sigkernel_corrector_features",
     "sigkernel_corrector_forward",
     "sigkernel_corrector_backward",
@@ -167,8 +167,8 @@ def load():
     i64, f32 = ctypes.c_int64, ctypes.c_float
     lib.sigkernel_corrector_param_count.argtypes = []
     lib.sigkernel_corrector_param_count.restype = i64
-    lib.sigkernel_corrector_act_floats.argtypes = []
-    lib.sigkernel_corrector_act_floats.restype = i64
+    lib.sigkernel_corrector_act_elems.argtypes = []
+    lib.sigkernel_corrector_act_elems.restype = i64
     lib.sigkernel_corrector_features.argtypes = [P, P, vp, vp, vp, vp, sz, vp]
     lib.sigkernel_corrector_features.restype = i32
     lib.sigkernel_corrector_forward.argtypes = [vp, vp, i64, vp, vp, vp]
@@ -179,7 +179,7 @@ def load():
     lib.sigkernel_corrector_loss.restype = i32
     lib.sigkernel_adam_step.argtypes = [vp, vp, vp, vp, i64, vp, f32, f32, f32, f32, vp]
     lib.sigkernel_adam_step.restype = i32
-    lib.sigkernel_channel_stats.argtypes = [vp, vp, i64, i32, vp, vp, vp, sz, vp]
+    lib.sigkernel_channel_stats.argtypes = [vp, i32, vp, i64, i32, vp, vp, vp, sz, vp]
     lib.sigkernel_channel_stats.restype = i32
     lib.sigkernel_corrector_predict.argtypes = [P, P, i32, vp, vp, vp, f32, f32, vp, vp, vp, vp,
                                                 sz, vp]

@@ -33,8 +33,8 @@ def param_count() -> int:
     return int(_lib.load().sigkernel_corrector_param_count())
 
 
-def act_floats() -> int:
-    return int(_lib.load().sigkernel_corrector_act_floats())
+def act_elems() -> int:
+    return int(_lib.load().sigkernel_corrector_act_elems())
 
 
 def init_params(seed: int) -> np.ndarray:
@@ -63,12 +63,12 @@ def _slice(X: torch.Tensor, a: int, b: int) -> torch.Tensor:
 def features(X: torch.Tensor, Y: torch.Tensor, norm: Optional[torch.Tensor] = None,
              feats: Optional[torch.Tensor] = None, k0: Optional[torch.Tensor] = None,
              workspace: Optional[torch.Tensor] = None):
-    """(feats [n, 64, 64, 8], k0 [n]) of the pairs (X_k, Y_k)."""
+    """(feats [n, 64, 64, 8] bf16, k0 [n]) of the pairs (X_k, Y_k)."""
     lib = _lib.load()
     n = int(X.shape[0])
     sx, sy = _describe(X), _describe(Y)
     if feats is None:
-        feats = torch.empty((n, 64, 64, 8), dtype=torch.float32, device=X.device)
+        feats = torch.empty((n, 64, 64, 8), dtype=torch.bfloat16, device=X.device)
     if k0 is None:
         k0 = torch.empty(n, dtype=torch.float32, device=X.device)
     nbytes = int(lib.sigkernel_workspace_bytes(_lib.SK_OP_CORRECTOR_FEATURES, ctypes.byref(sx),
@@ -84,11 +84,11 @@ def features(X: torch.Tensor, Y: torch.Tensor, norm: Optional[torch.Tensor] = No
 
 def forward(params: torch.Tensor, feats: torch.Tensor, acts: Optional[torch.Tensor] = None,
             y: Optional[torch.Tensor] = None):
-    """(acts, y [n, 2])."""
+    """(acts bf16, y [n, 2])."""
     n = int(feats.shape[0])
     dev = feats.device
     if acts is None:
-        acts = torch.empty(n * act_floats(), dtype=torch.float32, device=dev)
+        acts = torch.empty(n * act_elems(), dtype=torch.bfloat16, device=dev)
     if y is None:
         y = torch.empty((n, 2), dtype=torch.float32, device=dev)
     _lib.check(_lib.load().sigkernel_corrector_forward(params.data_ptr(), feats.data_ptr(), n,
@@ -148,7 +148,10 @@ def channel_stats(x: torch.Tensor, channels: int, sub: Optional[torch.Tensor] = 
     mean = torch.empty(channels, dtype=torch.float32, device=dev)
     rstd = torch.empty(channels, dtype=torch.float32, device=dev)
     ws = torch.empty(_lib.SK_CHANNEL_STATS_WORKSPACE_BYTES, dtype=torch.uint8, device=dev)
-    _lib.check(_lib.load().sigkernel_channel_stats(x.data_ptr(), _ptr(sub), rows, channels,
+    if x.dtype not in (torch.float32, torch.bfloat16):
+        raise TypeError("channel_stats reads float32 or bfloat16")
+    dt = 1 if x.dtype == torch.bfloat16 else 0
+    _lib.check(_lib.load().sigkernel_channel_stats(x.data_ptr(), dt, _ptr(sub), rows, channels,
                                                    mean.data_ptr(), rstd.data_ptr(),
                                                    ws.data_ptr(), ws.numel(), _stream_ptr(dev)),
                "sigkernel_channel_stats")
@@ -223,12 +226,12 @@ def fit_normalisation(X, Y, k_target, n_stats: int = 4096):
     dev = X.device
     n = int(X.shape[0])
     ns = min(n, n_stats)
-    feats, _ = features(_slice(X, 0, ns), _slice(Y, 0, ns))
+    feats, _ = features(_slice(X, 0, ns), _slice(Y, 0, ns))  # raw moments, bf16
     fmean, frstd = channel_stats(feats, 8)
     del feats
     k0 = torch.empty(n, dtype=torch.float32, device=dev)
     chunk = 4096
-    fbuf = torch.empty((chunk, 64, 64, 8), dtype=torch.float32, device=dev)
+    fbuf = torch.empty((chunk, 64, 64, 8), dtype=torch.bfloat16, device=dev)
     for a in range(0, n, chunk):
         b = min(n, a + chunk)
         features(_slice(X, a, b), _slice(Y, a, b), None, fbuf[:b - a], k0[a:b])
@@ -256,9 +259,9 @@ def train(X: torch.Tensor, Y: torch.Tensor, k_target: torch.Tensor, *, epochs: i
     m = torch.zeros(P, dtype=torch.float32, device=dev)
     v = torch.zeros(P, dtype=torch.float32, device=dev)
     step = torch.zeros(1, dtype=torch.int32, device=dev)
-    feats = torch.empty((batch, 64, 64, 8), dtype=torch.float32, device=dev)
+    feats = torch.empty((batch, 64, 64, 8), dtype=torch.bfloat16, device=dev)
     k0 = torch.empty(batch, dtype=torch.float32, device=dev)
-    acts = torch.empty(batch * act_floats(), dtype=torch.float32, device=dev)
+    acts = torch.empty(batch * act_elems(), dtype=torch.bfloat16, device=dev)
     y = torch.empty((batch, 2), dtype=torch.float32, device=dev)
     dy = torch.empty((batch, 2), dtype=torch.float32, device=dev)
     lbuf = torch.empty(1, dtype=torch.float32, device=dev)

@@ -411,7 +411,7 @@ size_t corrector_bwd_ws(int64_t n) {
 
 struct PredictLayout {
   PairLayout pl;
-  size_t feats, acts, y, k0, total;
+  size_t wb, feats, y, k0, total;
 };
 
 PredictLayout predict_layout(const sk_paths* X, const sk_paths* Y, int32_t lam) {
@@ -419,10 +419,10 @@ PredictLayout predict_layout(const sk_paths* X, const sk_paths* Y, int32_t lam) 
   L.pl = pair_layout(X, Y, lam, false);
   const size_t n = (size_t)X->n_paths;
   size_t off = L.pl.total;
+  L.wb = off;
+  off += align256((size_t)sk::corr::kHeadOffset * sizeof(uint16_t));
   L.feats = off;
-  off += align256(n * sk::corr::kFeatFloats * sizeof(float));
-  L.acts = off;
-  off += align256(n * (size_t)sk::corr::kActFloats * sizeof(float));
+  off += align256(n * sk::corr::kFeatFloats * sizeof(uint16_t));
   L.y = off;
   off += align256(n * 2 * sizeof(float));
   L.k0 = off;
@@ -445,10 +445,10 @@ sk_status corrector_increments(const sk_paths* X, const sk_paths* Y, char* base,
   return SK_OK;
 }
 
-sk_status corrector_forward(const float* params, const float* feats, int64_t n, float* acts,
-                            float* y, hipStream_t st) {
+sk_status corrector_forward(const float* params, const sk::corr::bf16* feats, int64_t n,
+                            sk::corr::bf16* acts, float* y, hipStream_t st) {
   using namespace sk::corr;
-  const float* in = feats;
+  const bf16* in = feats;
   for (int l = 0; l < kLayers; ++l) {
     ConvArgs a{};
     a.in = in;
@@ -738,10 +738,10 @@ sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t 
 
 // ---- learned corrector ----------------------------------------------------
 int64_t sigkernel_corrector_param_count(void) { return sk::corr::kParams; }
-int64_t sigkernel_corrector_act_floats(void) { return sk::corr::kActFloats; }
+int64_t sigkernel_corrector_act_elems(void) { return sk::corr::kActFloats; }
 
 sk_status sigkernel_corrector_features(const sk_paths* X, const sk_paths* Y, const float* norm,
-                                       float* feats, float* k0, void* ws, size_t ws_bytes,
+                                       uint16_t* feats, float* k0, void* ws, size_t ws_bytes,
                                        void* stream) {
   if (sk_status c = check_corrector_batches(X, Y)) return c;
   if (X->n_paths == 0) return SK_OK;
@@ -757,23 +757,27 @@ sk_status sigkernel_corrector_features(const sk_paths* X, const sk_paths* Y, con
   fa.n = Y->len - 1;
   fa.npairs = X->n_paths;
   fa.norm = norm;
-  fa.feats = feats;
+  fa.feats = reinterpret_cast<sk::corr::bf16*>(feats);
   fa.k0 = k0;
   return sk::corr::launch_features(fa, X->dim, st) == hipSuccess ? SK_OK : SK_ERR_HIP;
 }
 
-sk_status sigkernel_corrector_forward(const float* params, const float* feats, int64_t n,
-                                      float* acts, float* y, void* stream) {
+sk_status sigkernel_corrector_forward(const float* params, const uint16_t* feats, int64_t n,
+                                      uint16_t* acts, float* y, void* stream) {
   if (n < 0) return SK_ERR_SHAPE;
   if (n == 0) return SK_OK;
   if (!params || !feats || !acts || !y) return SK_ERR_NULL;
-  return corrector_forward(params, feats, n, acts, y, static_cast<hipStream_t>(stream));
+  return corrector_forward(params, reinterpret_cast<const sk::corr::bf16*>(feats), n,
+                           reinterpret_cast<sk::corr::bf16*>(acts), y,
+                           static_cast<hipStream_t>(stream));
 }
 
-sk_status sigkernel_corrector_backward(const float* params, const float* feats, const float* acts,
-                                       const float* dy, int64_t n, float* grads, void* ws,
-                                       size_t ws_bytes, void* stream) {
+sk_status sigkernel_corrector_backward(const float* params, const uint16_t* feats_bits,
+                                       const uint16_t* acts_bits, const float* dy, int64_t n,
+                                       float* grads, void* ws, size_t ws_bytes, void* stream) {
   using namespace sk::corr;
+  const bf16* feats = reinterpret_cast<const bf16*>(feats_bits);
+  const bf16* acts = reinterpret_cast<const bf16*>(acts_bits);
   if (n < 0) return SK_ERR_SHAPE;
   if (!params || !grads || (n > 0 && (!feats || !acts || !dy))) return SK_ERR_NULL;
   const size_t need = corrector_bwd_ws(n);
@@ -835,13 +839,14 @@ sk_status sigkernel_adam_step(float* params, const float* grads, float* m, float
              : SK_ERR_HIP;
 }
 
-sk_status sigkernel_channel_stats(const float* x, const float* sub, int64_t rows, int32_t channels,
-                                  float* mean, float* rstd, void* ws, size_t ws_bytes,
-                                  void* stream) {
+sk_status sigkernel_channel_stats(const void* x, int32_t x_dtype, const float* sub, int64_t rows,
+                                  int32_t channels, float* mean, float* rstd, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  if (x_dtype != 0 && x_dtype != 1) return SK_ERR_FLAGS;
   if (rows < 1 || channels < 1 || channels > sk::corr::kMaxStatChannels) return SK_ERR_SHAPE;
   if (!x || !mean || !rstd) return SK_ERR_NULL;
   if (!ws || ws_bytes < sk::corr::kStatsWorkspaceBytes) return SK_ERR_WORKSPACE;
-  return sk::corr::launch_channel_stats(x, sub, rows, channels, mean, rstd,
+  return sk::corr::launch_channel_stats(x, x_dtype == 1, sub, rows, channels, mean, rstd,
                                         static_cast<double*>(ws),
                                         static_cast<hipStream_t>(stream)) == hipSuccess
              ? SK_OK
@@ -867,8 +872,8 @@ sk_status sigkernel_corrector_predict(const sk_paths* X, const sk_paths* Y, int3
   char* base = static_cast<char*>(ws);
   float *incx, *incy;
   if (sk_status c = corrector_increments(X, Y, base, &incx, &incy, st)) return c;
-  float* feats = reinterpret_cast<float*>(base + L.feats);
-  float* acts = reinterpret_cast<float*>(base + L.acts);
+  sk::corr::bf16* wb = reinterpret_cast<sk::corr::bf16*>(base + L.wb);
+  sk::corr::bf16* feats = reinterpret_cast<sk::corr::bf16*>(base + L.feats);
   float* y = reinterpret_cast<float*>(base + L.y);
   float* k0 = reinterpret_cast<float*>(base + L.k0);
   sk::corr::FeatArgs fa{};
@@ -881,7 +886,16 @@ sk_status sigkernel_corrector_predict(const sk_paths* X, const sk_paths* Y, int3
   fa.feats = feats;
   fa.k0 = k0;
   if (sk::corr::launch_features(fa, X->dim, st) != hipSuccess) return SK_ERR_HIP;
-  if (sk_status c = corrector_forward(params, feats, n, acts, y, st)) return c;
+  // weights to bf16 once per call, then the whole network per pair on chip
+  if (sk::corr::launch_to_bf16(params, sk::corr::kHeadOffset, wb, st) != hipSuccess)
+    return SK_ERR_HIP;
+  sk::corr::NetArgs na{};
+  na.feats = feats;
+  na.wb = wb;
+  na.params = params;
+  na.n = n;
+  na.y = y;
+  if (sk::corr::launch_net_fused(na, st) != hipSuccess) return SK_ERR_HIP;
   int32_t* order = reinterpret_cast<int32_t*>(base + L.pl.order);
   int32_t* counts = reinterpret_cast<int32_t*>(base + L.pl.counts);
   sk::corr::DecideArgs da{};

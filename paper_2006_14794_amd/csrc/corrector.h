@@ -6,6 +6,8 @@
 namespace sk {
 namespace corr {
 
+using bf16 = __bf16;
+
 constexpr int kBlocks = 64;          // feature map side: 64 blocks of 4 x 4 coarse cells
 constexpr int kFeatChannels = 8;
 constexpr int kFeatFloats = kBlocks * kBlocks * kFeatChannels;
@@ -45,22 +47,30 @@ struct FeatArgs {
   int32_t m, n;        // coarse increments per x / y path, <= 256
   int64_t npairs;
   const float* norm;   // [16]: mean[8], 1/std[8] (nullptr: raw moments)
-  float* feats;        // [npairs][64][64][8]
+  bf16* feats;         // [npairs][64][64][8]
   float* k0;           // [npairs]: order-0 terminal value
 };
 
 struct ConvArgs {
-  const float* in;     // [n][HI][HI][Cin]
-  const float* w;      // [32][3][3][Cin]
+  const bf16* in;      // [n][HI][HI][Cin]
+  const float* w;      // [32][3][3][Cin] (rounded to bf16 on load)
   const float* b;      // [32]
-  float* out;          // [n][HI/2][HI/2][32], after ReLU
+  bf16* out;           // [n][HI/2][HI/2][32], after ReLU
   int64_t n;
 };
 
+struct NetArgs {
+  const bf16* feats;   // [n][64][64][8]
+  const bf16* wb;      // bf16 copy of the conv part of the parameters (same offsets)
+  const float* params; // biases and the head
+  int64_t n;
+  float* y;            // [n][2]
+};
+
 struct ConvBwdArgs {
-  const float* in;     // layer input
+  const bf16* in;      // layer input
   const float* w;
-  const float* out;    // layer output (after ReLU): the ReLU mask
+  const bf16* out;     // layer output (after ReLU): the ReLU mask
   const float* dout;   // gradient with respect to the output
   float* din;          // gradient with respect to the input
   float* partial;      // [nblocks][32 * 9 * Cin + 32]
@@ -86,16 +96,18 @@ hipError_t launch_features(const FeatArgs& a, int d, hipStream_t s);
 hipError_t launch_conv_fwd(int layer, const ConvArgs& a, hipStream_t s);
 hipError_t launch_conv_dx(int layer, const ConvBwdArgs& a, hipStream_t s);
 hipError_t launch_conv_dw(int layer, const ConvBwdArgs& a, float* grads, hipStream_t s);
-hipError_t launch_head_fwd(const float* act4, const float* wh, const float* bh, int64_t n,
+hipError_t launch_head_fwd(const bf16* act4, const float* wh, const float* bh, int64_t n,
                            float* y, hipStream_t s);
-hipError_t launch_head_bwd(const float* dy, const float* act4, const float* wh, int64_t n,
+hipError_t launch_head_bwd(const float* dy, const bf16* act4, const float* wh, int64_t n,
                            float* dact4, float* g_head, hipStream_t s);
+hipError_t launch_net_fused(const NetArgs& a, hipStream_t s);
+hipError_t launch_to_bf16(const float* x, int64_t n, bf16* y, hipStream_t s);
 hipError_t launch_loss(const float* y, const float* k_target, const float* k0, const float* tnorm,
                        int64_t n, float* loss, float* dy, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int32_t* step,
                        float lr, float b1, float b2, float eps, hipStream_t s);
-hipError_t launch_channel_stats(const float* x, const float* sub, int64_t rows, int C, float* mean,
-                                float* rstd, double* ws, hipStream_t s);
+hipError_t launch_channel_stats(const void* x, bool x_bf16, const float* sub, int64_t rows, int C,
+                                float* mean, float* rstd, double* ws, hipStream_t s);
 hipError_t launch_decide(const DecideArgs& a, hipStream_t s);
 
 }  // namespace corr

@@ -7,8 +7,11 @@
 //              grid on the fly: the grid itself never reaches memory.
 //   conv       3 x 3 / stride 2 / pad 1 layers on the matrix cores
 //              (v_mfma_f32_32x32x16_bf16: bf16 weights and activations,
-//              float32 accumulation), bias and ReLU fused; NHWC float32
-//              activations.
+//              float32 accumulation), bias and ReLU fused; NHWC bf16
+//              activations (every consumer reads them as bf16).
+//   fused      inference: one workgroup per pair runs all four layers and
+//              the head with the feature map, layer 1's output and each
+//              layer's weights in LDS.
 //   backward   float32 VALU: input gradients by gathering the (at most four)
 //              taps that reach an input pixel, weight gradients as
 //              per-workgroup partial sums over LDS-staged positions reduced
@@ -28,6 +31,7 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+using bf16 = __bf16;
 
 // ---------------------------------------------------------------- features --
 template <int D>
@@ -37,21 +41,21 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
   const int64_t pair = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (pair >= a.npairs) return;  // uniform per wave
   const int m = a.m, n = a.n;
-  float* __restrict__ fo = a.feats + pair * (int64_t)kFeatFloats;
+  bf16* __restrict__ fo = a.feats + pair * (int64_t)kFeatFloats;
   float mu[kFeatChannels], rs[kFeatChannels];
 #pragma unroll
   for (int c = 0; c < kFeatChannels; ++c) {
     mu[c] = a.norm ? a.norm[c] : 0.0f;
     rs[c] = a.norm ? a.norm[kFeatChannels + c] : 1.0f;
   }
-  // block (P, Q) of this lane's strip: moments f[0..5] plus coordinates
+  // block (P, Q) of this lane's strip: moments f[0..5] plus coordinates,
+  // normalised in float32 and stored as eight bf16 (16 bytes)
   auto put = [&](int P, int Q, const float (&f)[6]) {
-    float v[kFeatChannels] = {f[0], f[1], f[2], f[3], f[4], f[5], P / 63.0f, Q / 63.0f};
+    const float v[kFeatChannels] = {f[0], f[1], f[2], f[3], f[4], f[5], P / 63.0f, Q / 63.0f};
+    bf16x8 o;
 #pragma unroll
-    for (int c = 0; c < kFeatChannels; ++c) v[c] = (v[c] - mu[c]) * rs[c];
-    float4* dst = reinterpret_cast<float4*>(fo + ((int64_t)P * kBlocks + Q) * kFeatChannels);
-    dst[0] = make_float4(v[0], v[1], v[2], v[3]);
-    dst[1] = make_float4(v[4], v[5], v[6], v[7]);
+    for (int c = 0; c < kFeatChannels; ++c) o[c] = (bf16)((v[c] - mu[c]) * rs[c]);
+    *reinterpret_cast<bf16x8*>(fo + ((int64_t)P * kBlocks + Q) * kFeatChannels) = o;
   };
   const float zero6[6] = {0, 0, 0, 0, 0, 0};
   if (m <= 0 || n <= 0) {  // a one-point path: k = 1 and no cells
@@ -75,9 +79,13 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
 #pragma unroll
     for (int k = 0; k < D; ++k) dx[r][k] = t[k];
   }
+  // the scheme in double (the plain order-0 solve's arithmetic); the moments
+  // in float32 from one float copy of every node
   double u[4] = {1.0, 1.0, 1.0, 1.0};  // nodes K[p0 + r + 1][q] left of column q
+  float uf[4] = {1.0f, 1.0f, 1.0f, 1.0f};
   double pub = 1.0;                    // this lane's bottom node after its last column
   double up_last = 1.0;                // K[p0][q]: the upper-left node of row 0
+  float up_last_f = 1.0f;
   float f[6] = {0, 0, 0, 0, 0, 0};
   const float* __restrict__ ybase = a.incy + pair * (int64_t)n * DP;
   for (int t = 0; t < n + 63; ++t) {
@@ -86,9 +94,11 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
     // is K[p0][q + 1]; lane 0 reads the boundary row (value 1)
     const double up = fwd::from_prev_lane(pub, 1.0);
     if (q < 0 || q >= n) continue;
+    const float upf = (float)up;
     float dy[DP];
     fwd::load_row<DP>(ybase + (int64_t)q * DP, dy);
     double nv[4];
+    float nvf[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       float c = 0.0f;
@@ -97,21 +107,28 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
       const double A = u[r];
       const double B = (r == 0) ? up : nv[r - 1];
       const double C = (r == 0) ? up_last : u[r - 1];
-      const double S = A + B;
-      nv[r] = __builtin_fma(__builtin_fma((double)c, 0.5, 1.0), S, -C);
+      nv[r] = __builtin_fma(__builtin_fma((double)c, 0.5, 1.0), A + B, -C);
+      nvf[r] = (float)nv[r];
       if (p0 + r < m) {
-        const float s = (float)S;
+        const float Af = uf[r];
+        const float Bf = (r == 0) ? upf : nvf[r - 1];
+        const float Cf = (r == 0) ? up_last_f : uf[r - 1];
+        const float s = Af + Bf, cc = c * c;
         f[0] += c;
-        f[1] += c * c * s * 0.5f;
-        f[2] += c * s;
-        f[3] += (float)(C - 1.0);
-        f[4] += c * c * (float)C;
-        f[5] += c * (float)(B - A);
+        f[1] = __builtin_fmaf(cc * 0.5f, s, f[1]);
+        f[2] = __builtin_fmaf(c, s, f[2]);
+        f[3] += Cf - 1.0f;
+        f[4] = __builtin_fmaf(cc, Cf, f[4]);
+        f[5] = __builtin_fmaf(c, Bf - Af, f[5]);
       }
     }
     up_last = up;
+    up_last_f = upf;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) u[r] = nv[r];
+    for (int r = 0; r < 4; ++r) {
+      u[r] = nv[r];
+      uf[r] = nvf[r];
+    }
     pub = nv[3];
     if ((q & 3) == 3 || q == n - 1) {
       put(lane, q >> 2, f);
@@ -128,59 +145,54 @@ void* features_fn() {
   return reinterpret_cast<void*>(&features_kernel<D>);
 }
 
-// -------------------------------------------------------------- conv fwd --
-__device__ __forceinline__ bf16x8 to_bf16x8(const float (&v)[8]) {
+// ------------------------------------------------------------- conv tile --
+__device__ __forceinline__ bf16x8 load8(const bf16* p) {
+  return *reinterpret_cast<const bf16x8*>(p);
+}
+__device__ __forceinline__ bf16x8 load8(const float* p) {
+  const float4 x0 = reinterpret_cast<const float4*>(p)[0];
+  const float4 x1 = reinterpret_cast<const float4*>(p)[1];
   bf16x8 r;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) r[j] = (__bf16)v[j];
+  r[0] = (bf16)x0.x; r[1] = (bf16)x0.y; r[2] = (bf16)x0.z; r[3] = (bf16)x0.w;
+  r[4] = (bf16)x1.x; r[5] = (bf16)x1.y; r[6] = (bf16)x1.z; r[7] = (bf16)x1.w;
   return r;
 }
 
-__device__ __forceinline__ float bf16r(float v) { return (float)(__bf16)v; }
+__device__ __forceinline__ float bf16r(float v) { return (float)(bf16)v; }
 
-// One wave: 32 output positions x 32 output channels.  Lane l supplies
-// position (l mod 32) of the A tile and output channel (l mod 32) of the B
-// tile; its half (l / 32) selects 8 of the 16 reduction indices of an
-// instruction: for Cin = 32 one tap's channels c0 + 8 half .. + 8, for Cin = 8
-// tap 2 s + half of instruction s (a tenth tap is zero).
-template <int CIN, int HI>
-__global__ __launch_bounds__(256) void conv_fwd_kernel(const ConvArgs a) {
+// Tile t of one pair's layer: 32 output positions (raster order, t*32 ..) x
+// 32 output channels in acc.  Lane l supplies position (l mod 32) of the A
+// tile and output channel (l mod 32) of the B tile; its half (l / 32)
+// selects 8 of the 16 reduction indices of an instruction: for Cin = 32 one
+// tap's channels c0 + 8 half .. + 8, for Cin = 8 tap 2 s + half of
+// instruction s (a tenth tap is zero).  `in` is the pair's [HI][HI][Cin]
+// bf16 map and `w` the layer's [32][9][Cin] weights (bf16, or float32
+// rounded on load), either in global memory or in LDS.
+template <int CIN, int HI, class TW>
+__device__ __forceinline__ void conv_tile(const bf16* in, const TW* w, int t, int lane,
+                                          f32x16& acc) {
   constexpr int HO = HI / 2, PPP = HO * HO;
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t T = a.n * PPP;
-  const int64_t pos0 = wave * 32;
-  if (pos0 >= T) return;
   const int row = lane & 31, half = lane >> 5;
-  const int64_t pos = pos0 + row;
-  const bool valid = pos < T;
-  const int64_t pn = valid ? pos / PPP : 0;
-  const int rem = valid ? (int)(pos - pn * PPP) : 0;
-  const int ho = rem / HO, wo = rem - (rem / HO) * HO;
-  const float* __restrict__ inp = a.in + pn * (int64_t)(HI * HI * CIN);
+  const int pos = t * 32 + row;
+  const bool valid = pos < PPP;
+  const int ho = pos / HO, wo = pos - (pos / HO) * HO;
   auto a_op = [&](int tap, int c0) -> bf16x8 {
-    float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int kh = tap / 3, kw = tap - (tap / 3) * 3;
     const int hi = 2 * ho - 1 + kh, wi = 2 * wo - 1 + kw;
-    if (valid && tap < 9 && hi >= 0 && hi < HI && wi >= 0 && wi < HI) {
-      const float4* p = reinterpret_cast<const float4*>(inp + ((hi * HI + wi) * CIN + c0));
-      const float4 x0 = p[0], x1 = p[1];
-      v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
-      v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
-    }
-    return to_bf16x8(v);
+    if (valid && tap < 9 && hi >= 0 && hi < HI && wi >= 0 && wi < HI)
+      return load8(in + ((hi * HI + wi) * CIN + c0));
+    bf16x8 z;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) z[j] = (bf16)0.0f;
+    return z;
   };
   auto b_op = [&](int tap, int c0) -> bf16x8 {
-    float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (tap < 9) {
-      const float4* p = reinterpret_cast<const float4*>(a.w + ((row * 9 + tap) * CIN + c0));
-      const float4 x0 = p[0], x1 = p[1];
-      v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
-      v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
-    }
-    return to_bf16x8(v);
+    if (tap < 9) return load8(w + ((row * 9 + tap) * CIN + c0));
+    bf16x8 z;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) z[j] = (bf16)0.0f;
+    return z;
   };
-  f32x16 acc = {};
   if constexpr (CIN == 8) {
 #pragma unroll
     for (int s = 0; s < 5; ++s)
@@ -196,19 +208,128 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const ConvArgs a) {
                                                       b_op(tap, c0 + 8 * half), acc, 0, 0, 0);
     }
   }
-  const float bias = a.b[row];
+}
+
+// bias + ReLU, rounded to bf16: out[pos][co] of the tile's valid positions
+template <int PPP>
+__device__ __forceinline__ void store_tile(const f32x16& acc, float bias, bf16* out, int t,
+                                           int lane) {
+  const int half = lane >> 5, co = lane & 31;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int64_t p = pos0 + 8 * (r >> 2) + 4 * half + (r & 3);
-    if (p < T) a.out[p * kCout + row] = fmaxf(acc[r] + bias, 0.0f);
+    const int p = t * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+    if (p < PPP) out[p * kCout + co] = (bf16)fmaxf(acc[r] + bias, 0.0f);
   }
+}
+
+// Training / standalone forward of one layer: wave w = (pair, tile).
+template <int CIN, int HI>
+__global__ __launch_bounds__(256) void conv_fwd_kernel(const ConvArgs a) {
+  constexpr int HO = HI / 2, PPP = HO * HO, TPP = (PPP + 31) / 32;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wave >= a.n * TPP) return;
+  const int64_t pn = wave / TPP;
+  const int t = (int)(wave - pn * TPP);
+  f32x16 acc = {};
+  conv_tile<CIN, HI>(a.in + pn * (int64_t)(HI * HI * CIN), a.w, t, lane, acc);
+  store_tile<PPP>(acc, a.b[lane & 31], a.out + pn * (int64_t)(PPP * kCout), t, lane);
+}
+
+// ------------------------------------------------------ fused inference --
+// One workgroup (8 waves) per pair: the feature map, layer 1's output and the
+// current layer's weights stay in LDS; layers 2-4 reuse the feature map's
+// space; only the two outputs leave the chip.
+constexpr int kNetThreads = 512;
+constexpr int kLdsF = kFeatFloats;              // feature map, later layers 2-4
+constexpr int kLdsA1 = 32 * 32 * kCout;         // layer 1 output
+constexpr int kLdsW = kCout * 9 * 32;           // one layer's weights
+
+template <int CIN>
+__device__ __forceinline__ void stage_weights(bf16* W, const bf16* src, int tid) {
+  constexpr int N16 = kCout * 9 * CIN / 8;  // 16-byte chunks
+  for (int i = tid; i < N16; i += kNetThreads)
+    reinterpret_cast<uint4*>(W)[i] = reinterpret_cast<const uint4*>(src)[i];
+}
+
+__global__ __launch_bounds__(kNetThreads) void net_fused_kernel(const NetArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16 lds[kLdsF + kLdsA1 + kLdsW];
+  bf16* F = lds;
+  bf16* A1 = lds + kLdsF;
+  bf16* W = lds + kLdsF + kLdsA1;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int64_t pn = blockIdx.x;
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(a.feats + pn * (int64_t)kFeatFloats);
+    for (int i = tid; i < kFeatFloats / 8; i += kNetThreads) reinterpret_cast<uint4*>(F)[i] = src[i];
+  }
+  stage_weights<8>(W, a.wb + param_offset(0), tid);
+  __syncthreads();
+  for (int t = wid; t < 32; t += 8) {  // layer 1: 64 x 64 x 8 -> 32 x 32 x 32
+    f32x16 acc = {};
+    conv_tile<8, 64>(F, W, t, lane, acc);
+    store_tile<32 * 32>(acc, a.params[param_offset(0) + kCout * 9 * 8 + (lane & 31)], A1, t, lane);
+  }
+  __syncthreads();
+  stage_weights<32>(W, a.wb + param_offset(1), tid);
+  __syncthreads();
+  bf16* A2 = F;                 // 16 x 16 x 32
+  bf16* A3 = F + 16 * 16 * 32;  // 8 x 8 x 32
+  bf16* A4 = A3 + 8 * 8 * 32;   // 4 x 4 x 32
+  {
+    f32x16 acc = {};
+    conv_tile<32, 32>(A1, W, wid, lane, acc);
+    store_tile<16 * 16>(acc, a.params[param_offset(1) + kCout * 9 * 32 + (lane & 31)], A2, wid,
+                        lane);
+  }
+  __syncthreads();
+  stage_weights<32>(W, a.wb + param_offset(2), tid);
+  __syncthreads();
+  if (wid < 2) {
+    f32x16 acc = {};
+    conv_tile<32, 16>(A2, W, wid, lane, acc);
+    store_tile<8 * 8>(acc, a.params[param_offset(2) + kCout * 9 * 32 + (lane & 31)], A3, wid, lane);
+  }
+  __syncthreads();
+  stage_weights<32>(W, a.wb + param_offset(3), tid);
+  __syncthreads();
+  if (wid == 0) {
+    f32x16 acc = {};
+    conv_tile<32, 8>(A3, W, 0, lane, acc);
+    store_tile<4 * 4>(acc, a.params[param_offset(3) + kCout * 9 * 32 + (lane & 31)], A4, 0, lane);
+  }
+  __syncthreads();
+  if (wid == 0) {  // head, in the order of head_fwd_kernel
+    const float* __restrict__ wh = a.params + kHeadOffset;
+    float s0 = 0.0f, s1 = 0.0f;
+    for (int k = lane; k < kHeadIn; k += 64) {
+      const float x = (float)A4[k];
+      s0 = __builtin_fmaf(x, wh[k], s0);
+      s1 = __builtin_fmaf(x, wh[kHeadIn + k], s1);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s0 += __shfl_xor(s0, off, 64);
+      s1 += __shfl_xor(s1, off, 64);
+    }
+    if (lane == 0) {
+      a.y[2 * pn] = s0 + wh[2 * kHeadIn];
+      a.y[2 * pn + 1] = s1 + wh[2 * kHeadIn + 1];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float* __restrict__ x, int64_t n,
+                                                      bf16* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (bf16)x[i];
 }
 
 // ---------------------------------------------------------- conv backward --
 // Gradient of the pre-activation at output element e: dout where the ReLU
 // passed (out > 0), else 0.
-__device__ __forceinline__ float dpre(const float* out, const float* dout, int64_t e) {
-  return out[e] > 0.0f ? dout[e] : 0.0f;
+__device__ __forceinline__ float dpre(const bf16* out, const float* dout, int64_t e) {
+  return (float)out[e] > 0.0f ? dout[e] : 0.0f;
 }
 
 template <int CIN, int HI>
@@ -271,7 +392,7 @@ __global__ __launch_bounds__(256) void conv_dw_kernel(const ConvBwdArgs a) {
         const int rem = (int)(p - pn * PPP);
         const int hi = 2 * (rem / HO) - 1 + tap / 3, wi = 2 * (rem % HO) - 1 + tap % 3;
         if (hi >= 0 && hi < HI && wi >= 0 && wi < HI)
-          v = bf16r(a.in[((pn * HI + hi) * HI + wi) * CIN + ci]);
+          v = (float)a.in[((pn * HI + hi) * HI + wi) * CIN + ci];
       }
       sp[pp][r] = v;
     }
@@ -307,18 +428,19 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __res
 }
 
 // ------------------------------------------------------------------- head --
-__global__ __launch_bounds__(256) void head_fwd_kernel(const float* __restrict__ act4,
+__global__ __launch_bounds__(256) void head_fwd_kernel(const bf16* __restrict__ act4,
                                                        const float* __restrict__ wh,
                                                        const float* __restrict__ bh, int64_t n,
                                                        float* __restrict__ y) {
   const int lane = threadIdx.x & 63;
   const int64_t pn = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (pn >= n) return;
-  const float* __restrict__ x = act4 + pn * kHeadIn;
+  const bf16* __restrict__ x = act4 + pn * kHeadIn;
   float s0 = 0.0f, s1 = 0.0f;
   for (int k = lane; k < kHeadIn; k += 64) {
-    s0 = __builtin_fmaf(x[k], wh[k], s0);
-    s1 = __builtin_fmaf(x[k], wh[kHeadIn + k], s1);
+    const float xv = (float)x[k];
+    s0 = __builtin_fmaf(xv, wh[k], s0);
+    s1 = __builtin_fmaf(xv, wh[kHeadIn + k], s1);
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -343,14 +465,15 @@ __global__ __launch_bounds__(256) void head_dx_kernel(const float* __restrict__ 
 
 // grads of the head: [2][512] weights then [2] biases, summed over pairs in order
 __global__ __launch_bounds__(256) void head_dw_kernel(const float* __restrict__ dy,
-                                                      const float* __restrict__ act4, int64_t n,
+                                                      const bf16* __restrict__ act4, int64_t n,
                                                       float* __restrict__ g) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 2 * kHeadIn + 2) return;
   float s = 0.0f;
   if (e < 2 * kHeadIn) {
     const int o = e / kHeadIn, k = e - (e / kHeadIn) * kHeadIn;
-    for (int64_t pn = 0; pn < n; ++pn) s = __builtin_fmaf(dy[2 * pn + o], act4[pn * kHeadIn + k], s);
+    for (int64_t pn = 0; pn < n; ++pn)
+      s = __builtin_fmaf(dy[2 * pn + o], (float)act4[pn * kHeadIn + k], s);
   } else {
     const int o = e - 2 * kHeadIn;
     for (int64_t pn = 0; pn < n; ++pn) s += dy[2 * pn + o];
@@ -412,7 +535,8 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p,
 constexpr int kStatBlocks = 256;
 
 // pass 0: per-block sums of v = x (- sub); pass 1: of (v - mean)^2 (mean from ws)
-__global__ __launch_bounds__(256) void stats_partial_kernel(const float* __restrict__ x,
+template <class T>
+__global__ __launch_bounds__(256) void stats_partial_kernel(const T* __restrict__ x,
                                                             const float* __restrict__ sub,
                                                             int64_t rows, int C, int pass,
                                                             double* __restrict__ ws) {
@@ -492,9 +616,10 @@ __global__ void zero_i32_kernel(int32_t* p, int n) {
 template <int CIN, int HI>
 struct Layer {
   static hipError_t fwd(const ConvArgs& a, hipStream_t s) {
-    const int64_t tiles = (a.n * (HI / 2) * (HI / 2) + 31) / 32;
-    if (tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((conv_fwd_kernel<CIN, HI>), dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0,
+    constexpr int64_t TPP = ((HI / 2) * (HI / 2) + 31) / 32;
+    const int64_t waves = a.n * TPP;
+    if (waves == 0) return hipSuccess;
+    hipLaunchKernelGGL((conv_fwd_kernel<CIN, HI>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0,
                        s, a);
     return hipGetLastError();
   }
@@ -583,7 +708,7 @@ hipError_t launch_conv_dw(int layer, const ConvBwdArgs& a, float* grads, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_head_fwd(const float* act4, const float* wh, const float* bh, int64_t n,
+hipError_t launch_head_fwd(const bf16* act4, const float* wh, const float* bh, int64_t n,
                            float* y, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(head_fwd_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, act4, wh, bh,
@@ -591,7 +716,7 @@ hipError_t launch_head_fwd(const float* act4, const float* wh, const float* bh, 
   return hipGetLastError();
 }
 
-hipError_t launch_head_bwd(const float* dy, const float* act4, const float* wh, int64_t n,
+hipError_t launch_head_bwd(const float* dy, const bf16* act4, const float* wh, int64_t n,
                            float* dact4, float* g_head, hipStream_t s) {
   if (n > 0) {
     hipLaunchKernelGGL(head_dx_kernel, dim3((unsigned)((n * kHeadIn + 255) / 256)), dim3(256), 0, s,
@@ -617,13 +742,29 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
   return hipGetLastError();
 }
 
-hipError_t launch_channel_stats(const float* x, const float* sub, int64_t rows, int C, float* mean,
-                                float* rstd, double* ws, hipStream_t s) {
+hipError_t launch_channel_stats(const void* x, bool x_bf16, const float* sub, int64_t rows, int C,
+                                float* mean, float* rstd, double* ws, hipStream_t s) {
   for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(stats_partial_kernel, dim3(kStatBlocks), dim3(256), 0, s, x, sub, rows, C,
-                       pass, ws);
+    if (x_bf16)
+      hipLaunchKernelGGL(stats_partial_kernel<bf16>, dim3(kStatBlocks), dim3(256), 0, s,
+                         static_cast<const bf16*>(x), sub, rows, C, pass, ws);
+    else
+      hipLaunchKernelGGL(stats_partial_kernel<float>, dim3(kStatBlocks), dim3(256), 0, s,
+                         static_cast<const float*>(x), sub, rows, C, pass, ws);
     hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(64), 0, s, rows, C, pass, ws, mean, rstd);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_net_fused(const NetArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(net_fused_kernel, dim3((unsigned)a.n), dim3(kNetThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float* x, int64_t n, bf16* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, y);
   return hipGetLastError();
 }
 
