@@ -79,8 +79,11 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
 #pragma unroll
     for (int k = 0; k < D; ++k) dx[r][k] = t[k];
   }
-  // the scheme in double (the plain order-0 solve's arithmetic); the moments
-  // in float32 from one float copy of every node
+  // The scheme in double (the plain order-0 solve's arithmetic); the moments
+  // in float32 from one float copy of every node.  The y increment row that
+  // lane l needs at step t (row t - l) is the one lane l-1 used at step t-1:
+  // rows travel down the wave by DPP, and only row t itself is loaded, by a
+  // broadcast load (the same address in every lane) issued one step ahead.
   double u[4] = {1.0, 1.0, 1.0, 1.0};  // nodes K[p0 + r + 1][q] left of column q
   float uf[4] = {1.0f, 1.0f, 1.0f, 1.0f};
   double pub = 1.0;                    // this lane's bottom node after its last column
@@ -88,15 +91,30 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
   float up_last_f = 1.0f;
   float f[6] = {0, 0, 0, 0, 0, 0};
   const float* __restrict__ ybase = a.incy + pair * (int64_t)n * DP;
-  for (int t = 0; t < n + 63; ++t) {
+  auto fetch = [&](int q, float (&row)[DP]) {
+    if (q < n) {
+      fwd::load_row<DP>(ybase + (int64_t)q * DP, row);
+    } else {
+#pragma unroll
+      for (int k = 0; k < DP; ++k) row[k] = 0.0f;
+    }
+  };
+  float dy[DP];
+#pragma unroll
+  for (int k = 0; k < DP; ++k) dy[k] = 0.0f;
+  auto step = [&](int t, const float (&fresh)[DP], float (&next)[DP]) {
     const int q = t - lane;
+    fetch(t + 1, next);
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      dy[k] = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fresh[k]),
+                                                         __float_as_int(dy[k]), 0x138, 0xF, 0xF,
+                                                         false));
     // lane l-1 finished column q at the previous step: its bottom node there
     // is K[p0][q + 1]; lane 0 reads the boundary row (value 1)
     const double up = fwd::from_prev_lane(pub, 1.0);
-    if (q < 0 || q >= n) continue;
+    if (q < 0 || q >= n) return;
     const float upf = (float)up;
-    float dy[DP];
-    fwd::load_row<DP>(ybase + (int64_t)q * DP, dy);
     double nv[4];
     float nvf[4];
 #pragma unroll
@@ -113,12 +131,12 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
         const float Af = uf[r];
         const float Bf = (r == 0) ? upf : nvf[r - 1];
         const float Cf = (r == 0) ? up_last_f : uf[r - 1];
-        const float s = Af + Bf, cc = c * c;
+        const float s = Af + Bf, c2 = c * c;
         f[0] += c;
-        f[1] = __builtin_fmaf(cc * 0.5f, s, f[1]);
+        f[1] = __builtin_fmaf(c2 * 0.5f, s, f[1]);
         f[2] = __builtin_fmaf(c, s, f[2]);
         f[3] += Cf - 1.0f;
-        f[4] = __builtin_fmaf(cc, Cf, f[4]);
+        f[4] = __builtin_fmaf(c2, Cf, f[4]);
         f[5] = __builtin_fmaf(c, Bf - Af, f[5]);
       }
     }
@@ -136,6 +154,13 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
       for (int k = 0; k < 6; ++k) f[k] = 0.0f;
     }
     if (q == n - 1 && lane == (m - 1) >> 2) a.k0[pair] = (float)nv[(m - 1) & 3];
+  };
+  float dyA[DP], dyB[DP];
+  fetch(0, dyA);
+  const int nsteps = n + 63;
+  for (int t = 0; t < nsteps; t += 2) {
+    step(t, dyA, dyB);
+    if (t + 1 < nsteps) step(t + 1, dyB, dyA);
   }
   for (int Q = (n + 3) >> 2; Q < kBlocks; ++Q) put(lane, Q, zero6);
 }
