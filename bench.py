@@ -186,6 +186,15 @@ def bench_ragged(args):
     per, wall = time_steps(step, args.steps, args.warmup)
     ms = wall * 1e3 / args.steps
     cells = sum(((len(a) - 1) << lam) * ((len(b) - 1) << lam) for a, b in zip(xs, ys))
+    # the same pairs with bf16-rounded increments (float32 products and sums)
+    out16 = torch.empty_like(out)
+
+    def step16():
+        sk.sigkernel_pair(X, Y, lam, gram_precision="bf16", out=out16, workspace=ws)
+    per16, wall16 = time_steps(step16, args.steps, args.warmup)
+    d = xs[0].shape[1]
+    ops = cells * sweep_ops_per_cell(d, lam)
+    avg_s = float(np.mean(per)) / 1e3
     rec = {
         "metric": "Goursat grid-cell updates/s, batched uneven lengths",
         "value": cells / (ms / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
@@ -195,6 +204,11 @@ def bench_ragged(args):
                    "fine_cells": cells},
         "pairs_per_s": len(xs) / (ms / 1e3),
         "avg_event_ms": float(np.mean(per)), "launch": launch, "tuning": tune,
+        "bf16_increments_ms_per_step": wall16 * 1e3 / args.steps,
+        "roofline": {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": VALU_PEAK_TOPS,
+                     "unit": "Tops/s", "frac": ops / avg_s / 1e12 / VALU_PEAK_TOPS,
+                     "traffic": None, "kernel": "pair_kernel (events around each call)",
+                     "ops_per_cell": sweep_ops_per_cell(d, lam)},
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -207,11 +221,17 @@ def bench_ragged(args):
         dt = time.perf_counter() - t0
         scells = sum(((len(a) - 1) << lam) * ((len(b) - 1) << lam) for a, b in zip(sx, sy))
         got = out.cpu().numpy()[idx]
+        got16 = out16.cpu().numpy()[idx]
+
+        def errs(g):
+            e = np.abs(g - ref) / np.maximum(1, np.abs(ref))
+            return {"max": float(e.max()), "median": float(np.median(e))}
         rec["cpu_baseline"] = {
             "value": scells / dt, "unit": "cells/s", "cores": oracle.max_threads(),
             "kind": "oracle", "sample": f"{len(idx)} of the 4096 pairs, all host threads, "
                                         f"{dt:.2f} s",
-            "gpu_max_err_on_sample": float(np.max(np.abs(got - ref) / np.maximum(1, np.abs(ref))))}
+            "gpu_max_err_on_sample": errs(got)["max"]}
+        rec["err_vs_fp64_oracle"] = {"f32_increments": errs(got), "bf16_increments": errs(got16)}
     print(json.dumps(rec), flush=True)
 
 
@@ -275,6 +295,9 @@ def bench_corrector(args):
     k3 = plain.cpu().numpy().astype(np.float64)
     e = np.abs(out.cpu().numpy() - k3) / np.abs(k3)
     cells3 = n * (255 << 3) ** 2
+    # the network on the matrix cores: 3x3 convolutions, 32 output channels
+    # (layer 1's 72 reduction terms padded to 80), plus the dense head
+    macs = sum(o * o * 32 * k for o, k in ((32, 80), (16, 288), (8, 288), (4, 288))) + 2 * 512
     rec = {
         "metric": "order-3-equivalent grid-cell updates/s, learned corrector with fallback",
         "value": cells3 / (ms_l / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
@@ -287,6 +310,11 @@ def bench_corrector(args):
         "fallback_fraction": float(fb.float().mean().item()),
         "rel_err_vs_order3": {"median": float(np.median(e)),
                               "p99": float(np.percentile(e, 99)), "max": float(e.max())},
+        "network_mfma": {"flop_per_pair": 2 * macs, "unit": "TFLOP/s",
+                         "achieved_whole_call": 2 * macs * n / (ms_l / 1e3) / 1e12,
+                         "peak": 2500.0,
+                         "note": "whole predict call time; the fused network kernel's own "
+                                 "duration is in profiles/"},
     }
     print(json.dumps(rec), flush=True)
 
