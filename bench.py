@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="launch the library call every step instead of replaying its hipGraph")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (the known-size kernel that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch rules instead of autotuning (untimed) first")
     ap.add_argument("--cpu-sample-pairs", type=int, default=0,
@@ -62,6 +65,26 @@ def sweep_ops_per_cell(d: int, lam: int) -> float:
     FMAs per coarse cell, shared by 4^lam fine cells; a float FMA issues at
     twice the double rate, so it counts 1/2)."""
     return 2.0 + 0.5 * d / float(4 ** lam)
+
+
+SWEEP_SOURCES = ("sweep_fwd_kernel.h", "sweep_inst.h", "dispatch.h", "internal.h")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pmc_traffic_sweep_kernel_gram128_L256_d9_lam1.md")
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed counter summary, or None
+    when the sweep's sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        csrc = os.path.join(ROOT, "paper_2006_14794_amd", "csrc")
+        h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                    for f in SWEEP_SOURCES)).hexdigest()[:16]
+    except (OSError, AttributeError, ValueError):
+        return None
+    return rec["traffic_bytes"] if h == rec["source_hash"] else None
 
 
 def cpu_baseline(X, Y, lam, n_sample, K_gpu, repeats=3):
@@ -319,8 +342,25 @@ def bench_corrector(args):
     print(json.dumps(rec), flush=True)
 
 
+def copy_calibration(args):
+    """A plain device-to-device copy of 1 GiB, repeated: the reference
+    dispatch for the HBM byte counters."""
+    import torch
+    n = (1 << 30) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(max(1, args.steps)):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                      "dispatches": max(1, args.steps)}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
@@ -398,7 +438,7 @@ def main():
             "peak": VALU_PEAK_TOPS,
             "unit": "Tops/s",
             "frac": achieved / VALU_PEAK_TOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "kernel": "sweep_kernel (events around each step: increments + sweep)",
             "avg_launch_ms": avg_launch_s * 1e3,
             "ops_per_cell": sweep_ops_per_cell(d, lam),
