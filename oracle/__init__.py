@@ -11,7 +11,9 @@ Contents
 * ``libsko.so`` (built from ``sko.c``): the explicit scheme of eq.
   (explicit_finite_diff), Section 3.1, on the dyadic grid P_lambda of definition
   (fintite_diff), in IEEE double, plus its discrete adjoint and OpenMP loops over
-  the pairs of a batch or a Gram matrix.
+  the pairs of a batch or a Gram matrix; and the implicit scheme of the remark
+  after that equation (all four corners in the cell quadrature), solved for the
+  new corner cell by cell.
 * Pure-Python / NumPy pieces used to pin the solver:
   - ``bessel_series``: I_n(2z) = z^n sum_k z^{2k} / (k! (n+k)!), eq.
     (bessel_series), Appendix A.  With theorem (simple_Goursat_sol) the exact
@@ -79,6 +81,10 @@ def _load():
     lib.sko_gram_backward.argtypes = [dp, ip, i64, dp, ip, i64, i32, i32, dp, dp, dp,
                                       ctypes.c_int]
     lib.sko_gram_backward.restype = None
+    lib.sko_solve_implicit.argtypes = [dp, i64, dp, i64, i32, i32, dp]
+    lib.sko_solve_implicit.restype = ctypes.c_double
+    lib.sko_pairs_implicit.argtypes = [dp, ip, dp, ip, i64, i32, i32, dp, ctypes.c_int]
+    lib.sko_pairs_implicit.restype = None
     lib.sko_max_threads.argtypes = []
     lib.sko_max_threads.restype = ctypes.c_int
     _lib = lib
@@ -126,6 +132,31 @@ def solve(x, y, dyadic_order: int = 0) -> float:
     assert x.shape[1] == y.shape[1] and dyadic_order >= 0
     return float(_load().sko_solve(_dptr(x), x.shape[0], _dptr(y), y.shape[0],
                                    x.shape[1], int(dyadic_order), None))
+
+
+def solve_implicit(x, y, dyadic_order: int = 0, grid: bool = False):
+    """Terminal value (or all nodes with grid=True) of the implicit scheme of
+    the remark after eq. (explicit_finite_diff), on P_lambda."""
+    x, y = _path(x), _path(y)
+    assert x.shape[1] == y.shape[1] and dyadic_order >= 0
+    M = (x.shape[0] - 1) << dyadic_order
+    N = (y.shape[0] - 1) << dyadic_order
+    g = np.empty((M + 1, N + 1), dtype=np.float64) if grid else None
+    v = _load().sko_solve_implicit(_dptr(x), x.shape[0], _dptr(y), y.shape[0], x.shape[1],
+                                   int(dyadic_order), _dptr(g) if grid else None)
+    return g if grid else float(v)
+
+
+def pairs_implicit(xs, ys, dyadic_order: int = 0, nthreads: int = 0) -> np.ndarray:
+    """Independent pairs with the implicit scheme (OpenMP over pairs)."""
+    xf, xo, d = _pack(xs)
+    yf, yo, d2 = _pack(ys)
+    assert d == d2 and len(xo) == len(yo)
+    n = len(xo) - 1
+    out = np.empty(n, dtype=np.float64)
+    _load().sko_pairs_implicit(_dptr(xf), _iptr(xo), _dptr(yf), _iptr(yo), n, d,
+                               int(dyadic_order), _dptr(out), int(nthreads))
+    return out
 
 
 def solve_grid(x, y, dyadic_order: int = 0) -> np.ndarray:

@@ -115,6 +115,45 @@ double sko_solve(const double *x, int64_t lx, const double *y, int64_t ly,
     return result;
 }
 
+/* The implicit scheme of the remark after eq. (explicit_finite_diff): the
+ * double integral over a cell is estimated with all four corner values,
+ *     K11 = K10 + K01 - K00 + (1/4) inc (K00 + K10 + K01 + K11),
+ * which is linear in the unknown corner K11; solved for it cell by cell in the
+ * same row-major order, on the same refined grid and coefficients as
+ * sko_solve.  (A cell with inc = 4 has no solution: the division gives
+ * +-inf or NaN, which then propagates.) */
+double sko_solve_implicit(const double *x, int64_t lx, const double *y, int64_t ly,
+                          int32_t d, int32_t lam, double *grid)
+{
+    int64_t m = lx - 1, n = ly - 1;
+    int64_t M = m << lam, N = n << lam;
+    if (m <= 0 || n <= 0) {
+        if (grid)
+            for (int64_t k = 0; k < (M + 1) * (N + 1); ++k) grid[k] = 1.0;
+        return 1.0;
+    }
+    double *g0 = (double *)malloc((size_t)(m * n) * sizeof(double));
+    sko_increment_gram(x, lx, y, ly, d, g0);
+    double refine = ldexp(1.0, -2 * lam);
+    double *all = (double *)malloc((size_t)((M + 1) * (N + 1)) * sizeof(double));
+    for (int64_t j = 0; j <= N; ++j) all[j] = 1.0;
+    for (int64_t i = 0; i < M; ++i) {
+        double *prev = all + i * (N + 1), *cur = prev + (N + 1);
+        cur[0] = 1.0;
+        const double *g0row = g0 + (i >> lam) * n;
+        for (int64_t j = 0; j < N; ++j) {
+            double inc = g0row[j >> lam] * refine;
+            double K10 = cur[j], K01 = prev[j + 1], K00 = prev[j];
+            cur[j + 1] = (K10 + K01 - K00 + 0.25 * inc * (K00 + K10 + K01)) / (1.0 - 0.25 * inc);
+        }
+    }
+    double result = all[M * (N + 1) + N];
+    if (grid) memcpy(grid, all, (size_t)((M + 1) * (N + 1)) * sizeof(double));
+    free(all);
+    free(g0);
+    return result;
+}
+
 /* Value and gradient of K[M][N] with respect to every point of x and y.
  * Reverse accumulation through the row-major loop of sko_solve: cells are
  * visited in exactly the reverse order, and each cell pushes the adjoint of
@@ -202,6 +241,20 @@ void sko_pairs(const double *xs, const int64_t *xoff, const double *ys,
     for (int64_t k = 0; k < npairs; ++k) {
         out[k] = sko_solve(xs + xoff[k] * d, xoff[k + 1] - xoff[k],
                            ys + yoff[k] * d, yoff[k + 1] - yoff[k], d, lam, NULL);
+    }
+}
+
+/* Independent pairs with the implicit scheme. */
+void sko_pairs_implicit(const double *xs, const int64_t *xoff, const double *ys,
+                        const int64_t *yoff, int64_t npairs, int32_t d, int32_t lam,
+                        double *out, int nthreads)
+{
+    int nt = set_threads(nthreads);
+    (void)nt;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+    for (int64_t k = 0; k < npairs; ++k) {
+        out[k] = sko_solve_implicit(xs + xoff[k] * d, xoff[k + 1] - xoff[k],
+                                    ys + yoff[k] * d, yoff[k + 1] - yoff[k], d, lam, NULL);
     }
 }
 

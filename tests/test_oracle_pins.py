@@ -359,3 +359,73 @@ def test_mmd2_unbiased_definition_and_weights():
     assert abs(oracle.mmd2_unbiased(Kxx, Kyy, Kxy) - want) < 1e-14
     wxx, wyy, wxy = oracle.mmd2_weights(n, m)
     assert abs(np.sum(wxx * Kxx) + np.sum(wyy * Kyy) + np.sum(wxy * Kxy) - want) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Implicit scheme (remark after eq. explicit_finite_diff)
+# ---------------------------------------------------------------------------
+def _implicit_golden():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "implicit_one_cell.txt")):
+        if line.strip() and not line.startswith("#"):
+            c, num, den = line.split()
+            rows.append((float(c), int(num) / int(den)))
+    return rows
+
+
+def straight(a, b):
+    x = np.array([np.zeros_like(a), a])
+    y = np.array([np.zeros_like(b), b])
+    return x, y
+
+
+@pytest.mark.parametrize("c,expected", _implicit_golden())
+def test_implicit_one_cell_closed_form(c, expected):
+    # c = <a, b> with a = (c, 0), b = (1, 0)
+    x, y = straight(np.array([c, 0.0]), np.array([1.0, 0.0]))
+    assert abs(oracle.solve_implicit(x, y, 0) - expected) <= 1e-15 * max(1, abs(expected))
+
+
+def test_implicit_matches_bessel_series_to_second_order():
+    # one cell: (1 + 3c/4)/(1 - c/4) = 1 + c + c^2/4 + c^3/16 + ...; the exact
+    # kernel sum c^k/(k!)^2 = 1 + c + c^2/4 + c^3/36 + ...: they differ at c^3
+    for c in (1e-2, -1e-2, 3e-3):
+        x, y = straight(np.array([c, 0.0]), np.array([1.0, 0.0]))
+        diff = oracle.solve_implicit(x, y, 0) - oracle.straight_segment_kernel(c)
+        assert abs(diff - c ** 3 * (1 / 16 - 1 / 36)) <= 2 * abs(c) ** 4
+
+
+def test_implicit_converges_second_order_to_the_explicit_limit():
+    rng = np.random.default_rng(5)
+    x = np.cumsum(rng.normal(size=(6, 3)) * 0.5, axis=0)
+    y = np.cumsum(rng.normal(size=(5, 3)) * 0.5, axis=0)
+    lim = oracle.richardson(oracle.solve(x, y, 6), oracle.solve(x, y, 7))
+    errs = [abs(oracle.solve_implicit(x, y, lam) - lim) for lam in range(1, 6)]
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    assert all(3.5 < r < 4.5 for r in ratios[1:]), ratios
+
+
+def test_implicit_invariants():
+    rng = np.random.default_rng(6)
+    x = np.cumsum(rng.normal(size=(7, 2)) * 0.4, axis=0)
+    y = np.cumsum(rng.normal(size=(4, 2)) * 0.4, axis=0)
+    k = oracle.solve_implicit(x, y, 2)
+    assert abs(oracle.solve_implicit(y, x, 2) - k) <= 1e-13
+    assert abs(oracle.solve_implicit(x + 3.0, y - 1.0, 2) - k) <= 1e-12
+    assert oracle.solve_implicit(x[:1], y, 1) == 1.0
+    g = oracle.solve_implicit(x, y, 1, grid=True)
+    assert g.shape == (13, 7) and np.all(g[0] == 1.0) and np.all(g[:, 0] == 1.0)
+    # the cell relation holds at every cell of the grid (the solve, checked
+    # against its defining equation rather than its own rearrangement)
+    c = oracle.increment_gram(x, y) / 4.0
+    for i in range(12):
+        for j in range(6):
+            inc = c[i >> 1, j >> 1]
+            lhs = g[i + 1, j + 1]
+            rhs = g[i + 1, j] + g[i, j + 1] - g[i, j] + 0.25 * inc * (
+                g[i, j] + g[i + 1, j] + g[i, j + 1] + g[i + 1, j + 1])
+            assert abs(lhs - rhs) <= 1e-14 * max(1, abs(lhs))
+    xs = [x, y, x[:3]]
+    ys = [y, x, y[:2]]
+    assert np.allclose(oracle.pairs_implicit(xs, ys, 1),
+                       [oracle.solve_implicit(a, b, 1) for a, b in zip(xs, ys)], rtol=0, atol=0)
