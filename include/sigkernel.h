@@ -85,7 +85,13 @@ enum {
     SK_MMD2_GRAD = 1u << 2,   /* mmd2 only: also write the gradient with respect to X          */
     SK_GRAM_BF16 = 1u << 3,   /* pair / gram: increments rounded to bfloat16 before the inner
                                  products (16-bit inputs, float32 accumulation)                */
-    SK_GRAM_F16  = 1u << 4    /* pair / gram: the same with IEEE half                          */
+    SK_GRAM_F16  = 1u << 4,   /* pair / gram: the same with IEEE half                          */
+    SK_IMPLICIT  = 1u << 5    /* pair / gram: the implicit scheme of the remark after eq.
+                                 (explicit_finite_diff) -- the cell integral estimated with all
+                                 four corners, solved for the new corner:
+                                 K11 = (K10 + K01)(1 + c/4)/(1 - c/4) - K00, c the fine cell's
+                                 coefficient.  A cell with c = 4 has no solution (inf/NaN).  No
+                                 gradient (sigkernel_gram_backward rejects the flag)          */
 };
 
 /*

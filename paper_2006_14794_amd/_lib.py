@@ -28,6 +28,7 @@ SK_NO_DIAG = 1 << 1
 SK_MMD2_GRAD = 1 << 2
 SK_GRAM_BF16 = 1 << 3
 SK_GRAM_F16 = 1 << 4
+SK_IMPLICIT = 1 << 5
 
 SK_OP_PAIR = 0
 SK_OP_GRAM = 1

@@ -106,16 +106,24 @@ def _gram_flag(gram_precision: str) -> int:
     return _GRAM_PRECISION[gram_precision]
 
 
+def _scheme_flag(scheme: str) -> int:
+    if scheme not in ("explicit", "implicit"):
+        raise ValueError("scheme must be 'explicit' or 'implicit'")
+    return _lib.SK_IMPLICIT if scheme == "implicit" else 0
+
+
 def sigkernel_pair(x: PathsLike, y: PathsLike, dyadic_order: int = 0, *,
-                   gram_precision: str = "f32", out: Optional[torch.Tensor] = None,
+                   gram_precision: str = "f32", scheme: str = "explicit",
+                   out: Optional[torch.Tensor] = None,
                    workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """out[k] = k_hat(x_k, y_k) of the explicit scheme on P_lambda.
-    ``gram_precision`` 'bf16' / 'f16' rounds the increments to 16 bits before
-    their inner products (float32 accumulation)."""
+    """out[k] = k_hat(x_k, y_k) of the explicit (or, with scheme='implicit',
+    the implicit) scheme on P_lambda.  ``gram_precision`` 'bf16' / 'f16'
+    rounds the increments to 16 bits before their inner products (float32
+    accumulation)."""
     lib = _lib.load()
     dev = _device(x)
     n = _n_paths(x)
-    flags = _gram_flag(gram_precision)
+    flags = _gram_flag(gram_precision) | _scheme_flag(scheme)
     sx, sy = _describe(x), _describe(y)
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=dev)
@@ -131,7 +139,8 @@ def sigkernel_pair(x: PathsLike, y: PathsLike, dyadic_order: int = 0, *,
 
 def sigkernel_gram(X: PathsLike, Y: Optional[PathsLike] = None, dyadic_order: int = 0, *,
                    symmetric: bool = False, no_diag: bool = False,
-                   gram_precision: str = "f32", out: Optional[torch.Tensor] = None,
+                   gram_precision: str = "f32", scheme: str = "explicit",
+                   out: Optional[torch.Tensor] = None,
                    workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
     """K[a, b] = k_hat(X_a, Y_b).  ``symmetric=True`` (Y omitted or X itself)
     solves a <= b only and mirrors; ``no_diag`` then writes 0 on the diagonal."""
@@ -142,7 +151,7 @@ def sigkernel_gram(X: PathsLike, Y: Optional[PathsLike] = None, dyadic_order: in
         raise ValueError("symmetric Gram needs Y to be X")
     dev = _device(X)
     nx, ny = _n_paths(X), _n_paths(Y)
-    flags = _gram_flag(gram_precision)
+    flags = _gram_flag(gram_precision) | _scheme_flag(scheme)
     if symmetric:
         flags |= _lib.SK_SYMMETRIC
         if no_diag:

@@ -185,7 +185,7 @@ sk_status check_flags(uint32_t flags, uint32_t allowed) {
 // gram: every (a, b) of the two batches, out[a * ny + b]; else pairs (x_k, y_k)
 sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* out, void* ws,
                     size_t ws_bytes, hipStream_t stream, bool gram, int rounding,
-                    const sk_tune& tune) {
+                    const sk_tune& tune, bool implicit) {
   const int d = X->dim;
   const int dp = sk::padded_dim(d);
   const PairLayout PL = pair_layout(X, Y, lam, gram);
@@ -237,6 +237,7 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* ou
   a.x_len = X->len;
   a.y_len = Y->len;
   a.scale = ldexp(1.0, -(2 * lam + 1));
+  a.implicit = implicit ? 1 : 0;
   a.bandbuf = reinterpret_cast<double*>(base + PL.bands);
   a.band_stride = PL.band_stride;
   a.out = out;
@@ -264,7 +265,9 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_
                       float* out, void* ws, size_t ws_bytes, hipStream_t stream, int mode) {
   const int rounding = rounding_of(flags);
   const sk_tune tune = sk::tuning_for(mode == 0 ? SK_OP_PAIR : SK_OP_GRAM, X, Y, lam, flags);
-  if (mode == 0) return run_pairs(X, Y, lam, out, ws, ws_bytes, stream, false, rounding, tune);
+  const bool implicit = (flags & SK_IMPLICIT) != 0;
+  if (mode == 0)
+    return run_pairs(X, Y, lam, out, ws, ws_bytes, stream, false, rounding, tune, implicit);
   const int d = X->dim;
   const int dp = sk::padded_dim(d);
   const int64_t fine_rows = (int64_t)(X->len - 1) << lam;
@@ -273,7 +276,8 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_
     // x paths taller than one wave's strips: every (a, b) through the
     // persistent pair kernel with row bands (a symmetric Gram is filled in
     // both halves by solving both)
-    const sk_status st = run_pairs(X, Y, lam, out, ws, ws_bytes, stream, true, rounding, tune);
+    const sk_status st =
+        run_pairs(X, Y, lam, out, ws, ws_bytes, stream, true, rounding, tune, implicit);
     if (st == SK_OK && mode == 2 && (flags & SK_NO_DIAG) &&
         sk::launch_zero_diag(out, X->n_paths, stream) != hipSuccess)
       return SK_ERR_HIP;
@@ -314,6 +318,7 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_
   a.ny = Y->n_paths;
   a.mode = mode;
   a.no_diag = (flags & SK_NO_DIAG) ? 1 : 0;
+  a.implicit = implicit ? 1 : 0;
   a.out = out;
   a.out_ld = Y->n_paths;
   if (mode == 0) {
@@ -528,7 +533,7 @@ sk_status sigkernel_pair(const sk_paths* x, const sk_paths* y, int32_t dyadic_or
   if ((x->n_paths > 0 && !x->points) || (y->n_paths > 0 && !y->points)) return SK_ERR_NULL;
   if (x->dim != y->dim || x->n_paths != y->n_paths) return SK_ERR_SHAPE;
   if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
-  if (sk_status f = check_flags(flags, SK_GRAM_BF16 | SK_GRAM_F16)) return f;
+  if (sk_status f = check_flags(flags, SK_GRAM_BF16 | SK_GRAM_F16 | SK_IMPLICIT)) return f;
   if (x->n_paths == 0) return SK_OK;
   if (!ws) return SK_ERR_WORKSPACE;
   return run_forward(x, y, dyadic_order, flags, out, ws, ws_bytes,
@@ -543,7 +548,8 @@ sk_status sigkernel_gram(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
   if ((X->n_paths > 0 && !X->points) || (Y->n_paths > 0 && !Y->points)) return SK_ERR_NULL;
   if (X->dim != Y->dim) return SK_ERR_SHAPE;
   if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
-  if (sk_status f = check_flags(flags, SK_SYMMETRIC | SK_NO_DIAG | SK_GRAM_BF16 | SK_GRAM_F16))
+  if (sk_status f = check_flags(
+          flags, SK_SYMMETRIC | SK_NO_DIAG | SK_GRAM_BF16 | SK_GRAM_F16 | SK_IMPLICIT))
     return f;
   if ((flags & SK_SYMMETRIC) &&
       (X->points != Y->points || X->offsets != Y->offsets || X->n_paths != Y->n_paths ||

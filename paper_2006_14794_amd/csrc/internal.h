@@ -56,6 +56,7 @@ struct SweepArgs {
   int64_t nx, ny;           // paths per batch
   int32_t mode;             // 0: pairs (x_k, y_k); 1: Gram; 2: Gram upper triangle, mirrored
   int32_t no_diag;          // mode 2: diagonal written as 0
+  int32_t implicit;         // 1: the implicit scheme's cell factor (2 + h) / (2 - h)
   int32_t run;              // pairs streamed through one wave (Gram with uniform y)
   int64_t runs_per_row;     // ceil(ny / run)
   int64_t n_waves;
@@ -136,6 +137,7 @@ struct PairArgs {
   int64_t band_stride;
   float* out;               // out[pid]
   int64_t gram_ny;          // 0: pair pid is (x_pid, y_pid); else (x_{pid / gram_ny}, y_{pid % gram_ny})
+  int32_t implicit;         // 1: the implicit scheme's cell factor (2 + h) / (2 - h)
 };
 
 struct PairPlanArgs {

@@ -125,7 +125,10 @@ __global__ __launch_bounds__(256) void pair_kernel(const PairArgs a) {
         if ((uint32_t)g < (uint32_t)n) {
           double gk[CR];
 #pragma unroll
-          for (int c = 0; c < CR; ++c) gk[c] = __builtin_fma((double)h32[c], a.scale, 1.0);
+          for (int c = 0; c < CR; ++c) {
+            const double h = (double)h32[c] * a.scale;  // exact: scale is a power of two
+            gk[c] = a.implicit ? (2.0 + h) / (2.0 - h) : __builtin_fma((double)h32[c], a.scale, 1.0);
+          }
           double v[R][S];
 #pragma unroll
           for (int dgl = 0; dgl < R + S - 1; ++dgl) {

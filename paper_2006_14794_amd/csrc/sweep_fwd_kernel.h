@@ -25,7 +25,10 @@
 // g = 1 + G0 / 2^(2 lambda + 1),
 //     K' = fma(g, A + B, -C)  ==  A + B - C + (g - 1)(A + B),
 // two double operations per cell.  g is formed in double, where the rounding
-// of 1 + h perturbs h by at most 2^-53 in absolute value.
+// of 1 + h perturbs h by at most 2^-53 in absolute value.  The implicit scheme
+// of the remark after eq. (explicit_finite_diff) quadratures the cell with all
+// four corners; solved for the new corner it is the same update with
+// g = (1 + h/2) / (1 - h/2) = (2 + h) / (2 - h), formed once per coarse cell.
 #pragma once
 #include <math.h>
 
@@ -214,7 +217,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     if ((uint32_t)g < (uint32_t)total32) {
       double gk[CR];
 #pragma unroll
-      for (int c = 0; c < CR; ++c) gk[c] = 1.0 + (double)h32[c];
+      for (int c = 0; c < CR; ++c) {
+        const double h = (double)h32[c];
+        gk[c] = a.implicit ? (2.0 + h) / (2.0 - h) : 1.0 + h;
+      }
       // the R x S block of this step in antidiagonal order: S independent
       // dependency chains for the scheduler
       double v[R][S];

@@ -137,3 +137,15 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         _lib.load()
+
+
+def test_implicit_flag_only_where_defined():
+    lib = _lib.load()
+    X = paths()
+    # the backward, the MMD and the standalone increment Gram have no implicit form
+    assert lib.sigkernel_gram_backward(ctypes.byref(X), ctypes.byref(X), 1, _lib.SK_IMPLICIT,
+                                       FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == _lib.SK_ERR_FLAGS
+    assert lib.sigkernel_increment_gram(ctypes.byref(X), ctypes.byref(X), 1, _lib.SK_IMPLICIT,
+                                        FAKE, None) == _lib.SK_ERR_FLAGS
+    assert lib.sigkernel_mmd2(ctypes.byref(X), ctypes.byref(X), 1, _lib.SK_IMPLICIT, FAKE, FAKE,
+                              FAKE, 1 << 30, None) == _lib.SK_ERR_FLAGS
