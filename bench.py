@@ -46,6 +46,9 @@ def parse():
                          "scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch rules instead of autotuning (untimed) first")
+    ap.add_argument("--scheme", choices=["explicit", "implicit"], default="explicit",
+                    help="gram workload: the explicit scheme (default, the reported metric) or the "
+                         "implicit one")
     ap.add_argument("--cpu-sample-pairs", type=int, default=0,
                     help="pairs of the workload timed on the CPU oracle (0: all)")
     ap.add_argument("--workload", choices=["gram", "mmd", "ragged", "increment_gram", "corrector"],
@@ -87,11 +90,12 @@ def measured_traffic():
     return rec["traffic_bytes"] if h == rec["source_hash"] else None
 
 
-def cpu_baseline(X, Y, lam, n_sample, K_gpu, repeats=3):
+def cpu_baseline(X, Y, lam, n_sample, K_gpu, repeats=3, scheme="explicit"):
     """Time the FP64 oracle on the workload's pairs (all of them unless
     n_sample is given: a seeded sample), on all host threads, median of
     ``repeats`` runs, and report the GPU output's error on the same pairs."""
     import oracle
+    solve = oracle.pairs_implicit if scheme == "implicit" else oracle.pairs
     nx, ny = X.shape[0], Y.shape[0]
     if n_sample and n_sample < nx * ny:
         idx = np.random.default_rng(1).choice(nx * ny, size=n_sample, replace=False)
@@ -100,11 +104,11 @@ def cpu_baseline(X, Y, lam, n_sample, K_gpu, repeats=3):
     xs = [X[i // ny].astype(np.float64) for i in idx]
     ys = [Y[i % ny].astype(np.float64) for i in idx]
     threads = oracle.max_threads()
-    oracle.pairs(xs[:8], ys[:8], lam)  # load + warm
+    solve(xs[:8], ys[:8], lam)  # load + warm
     times = []
     for _ in range(repeats):
         t0 = time.perf_counter()
-        ref = oracle.pairs(xs, ys, lam, nthreads=threads)
+        ref = solve(xs, ys, lam, nthreads=threads)
         times.append(time.perf_counter() - t0)
     dt = float(np.median(times))
     cells = len(idx) * ((X.shape[1] - 1) << lam) * ((Y.shape[1] - 1) << lam)
@@ -390,16 +394,17 @@ def main():
     Xt = torch.from_numpy(X).to(dev)
     Yt = torch.from_numpy(Y).to(dev)
     # launch tuning is set-up: timed candidates run before the warm-up
-    tune = None if args.no_autotune else sk.autotune("gram", Xt, Yt, lam)[0]
+    scheme = args.scheme
+    tune = None if args.no_autotune else sk.autotune("gram", Xt, Yt, lam, scheme=scheme)[0]
     out = torch.empty((nx, ny), dtype=torch.float32, device=dev)
     ws = torch.empty(sk.workspace_bytes(1, Xt, Yt, lam, 0), dtype=torch.uint8, device=dev)
 
     def call():
-        sk.sigkernel_gram(Xt, Yt, lam, out=out, workspace=ws)
+        sk.sigkernel_gram(Xt, Yt, lam, scheme=scheme, out=out, workspace=ws)
 
     graph = None
     if not args.eager:
-        graph, out = sk.capture_gram(Xt, Yt, lam)
+        graph, out = sk.capture_gram(Xt, Yt, lam, scheme=scheme)
     step, launch = (call, "eager") if graph is None else (graph.replay, "hipGraph replay")
     # HIP events on the stream the step is launched on (torch's current stream)
     per_launch_ms, wall = time_steps(step, args.steps, args.warmup)
@@ -428,6 +433,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "gram 128x128 pairs, 256-point paths, d=8+time, dyadic order 1",
                    "pairs": nx * ny, "fine_cells_per_pair": M * N, "sweep_state": "f64",
+                   "scheme": scheme,
                    "increment_gram": "f32"},
         "pairs_per_s": pairs_per_s,
         "launch": launch,
@@ -446,7 +452,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         n_sample = args.cpu_sample_pairs
-        rec["cpu_baseline"] = cpu_baseline(X, Y, lam, n_sample, out.cpu().numpy())
+        rec["cpu_baseline"] = cpu_baseline(X, Y, lam, n_sample, out.cpu().numpy(),
+                                          scheme=scheme)
     print(json.dumps(rec), flush=True)
 
 

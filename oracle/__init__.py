@@ -25,6 +25,12 @@ Contents
     the inner product of definition 2.1 (Section 2).
   - ``mmd2_unbiased``: the unbiased MMD estimator mentioned at the end of
     Section 3.1.1 (U-statistic, diagonal terms excluded).
+* The static-kernel lift (eq. (PDE_lifted) and its finite-difference form):
+  ``static_kernel_matrix`` (RBF, linear or any callable kernel),
+  ``lifted_coefficients`` (its second difference over each coarse cell),
+  ``solve_coef`` (either scheme driven by a given coefficient matrix),
+  ``solve_lifted`` and the OpenMP batches ``lifted_rbf_pairs`` /
+  ``lifted_rbf_gram``.
 
 Every function here is pinned by ``tests/test_oracle_pins.py`` against
 something other than itself (hand-derived values, closed forms, library
@@ -85,6 +91,17 @@ def _load():
     lib.sko_solve_implicit.restype = ctypes.c_double
     lib.sko_pairs_implicit.argtypes = [dp, ip, dp, ip, i64, i32, i32, dp, ctypes.c_int]
     lib.sko_pairs_implicit.restype = None
+    lib.sko_static_rbf.argtypes = [dp, i64, dp, i64, i32, ctypes.c_double, dp]
+    lib.sko_static_rbf.restype = None
+    lib.sko_static_linear.argtypes = [dp, i64, dp, i64, i32, dp]
+    lib.sko_static_linear.restype = None
+    lib.sko_lifted_coefficients.argtypes = [dp, i64, i64, dp]
+    lib.sko_lifted_coefficients.restype = None
+    lib.sko_solve_coef.argtypes = [dp, i64, i64, i32, i32, dp]
+    lib.sko_solve_coef.restype = ctypes.c_double
+    lib.sko_lifted_rbf_batch.argtypes = [dp, ip, i64, dp, ip, i64, i32, i32, ctypes.c_double,
+                                         i32, i32, dp, ctypes.c_int]
+    lib.sko_lifted_rbf_batch.restype = None
     lib.sko_max_threads.argtypes = []
     lib.sko_max_threads.restype = ctypes.c_int
     _lib = lib
@@ -362,3 +379,90 @@ def local_error_bound_boundary_one(c: float) -> float:
         return sum(z ** k / (math.factorial(k) * math.factorial(k + 1)) for k in range(40)) - 1.0
     sup = max(abs(f(float(z))) for z in zs)
     return abs(c) * sup
+
+
+# ---------------------------------------------------------------------------
+# Static-kernel lift (eq. (PDE_lifted) and the finite-difference form after it)
+# ---------------------------------------------------------------------------
+def rbf(sigma: float) -> dict:
+    """The Gaussian static kernel exp(-|a - b|^2 / (2 sigma^2))."""
+    assert sigma > 0
+    return {"kind": "rbf", "sigma": float(sigma)}
+
+
+LINEAR = {"kind": "linear"}
+
+
+def static_kernel_matrix(x, y, kernel) -> np.ndarray:
+    """kappa(x_i, y_j) over all node pairs, shape (lx, ly).  ``kernel`` is
+    ``rbf(sigma)``, ``LINEAR``, or a callable (A [lx, d], B [ly, d]) -> matrix."""
+    x, y = _path(x), _path(y)
+    assert x.shape[1] == y.shape[1]
+    if callable(kernel):
+        return np.ascontiguousarray(np.asarray(kernel(x, y), dtype=np.float64))
+    k = np.empty((x.shape[0], y.shape[0]), dtype=np.float64)
+    if kernel["kind"] == "rbf":
+        _load().sko_static_rbf(_dptr(x), x.shape[0], _dptr(y), y.shape[0], x.shape[1],
+                               kernel["sigma"], _dptr(k))
+    elif kernel["kind"] == "linear":
+        _load().sko_static_linear(_dptr(x), x.shape[0], _dptr(y), y.shape[0], x.shape[1],
+                                  _dptr(k))
+    else:
+        raise ValueError(kernel)
+    return k
+
+
+def lifted_coefficients(x, y, kernel) -> np.ndarray:
+    """Coarse coefficients of the lifted scheme: the second difference of the
+    static-kernel matrix over each cell, shape (lx - 1, ly - 1)."""
+    k = static_kernel_matrix(x, y, kernel)
+    lx, ly = k.shape
+    c = np.zeros((max(lx - 1, 0), max(ly - 1, 0)), dtype=np.float64)
+    if lx > 1 and ly > 1:
+        _load().sko_lifted_coefficients(_dptr(k), lx, ly, _dptr(c))
+    return c
+
+
+def solve_coef(coef, dyadic_order: int = 0, scheme: str = "explicit", grid: bool = False):
+    """Either scheme on P_lambda driven by a coarse coefficient matrix [m, n]."""
+    coef = np.ascontiguousarray(np.asarray(coef, dtype=np.float64))
+    m, n = coef.shape
+    M, N = m << dyadic_order, n << dyadic_order
+    g = np.empty((M + 1, N + 1), dtype=np.float64) if grid else None
+    v = _load().sko_solve_coef(_dptr(coef) if coef.size else None, m, n, int(dyadic_order),
+                               1 if scheme == "implicit" else 0, _dptr(g) if grid else None)
+    return g if grid else float(v)
+
+
+def solve_lifted(x, y, dyadic_order: int = 0, kernel=None, scheme: str = "explicit",
+                 grid: bool = False):
+    """The lifted signature kernel of one pair (default kernel: RBF, sigma 1)."""
+    kernel = rbf(1.0) if kernel is None else kernel
+    return solve_coef(lifted_coefficients(x, y, kernel), dyadic_order, scheme, grid)
+
+
+def _lifted_rbf_batch(X, Y, dyadic_order, sigma, scheme, gram, nthreads):
+    xf, xo, d = _pack(X)
+    yf, yo, d2 = _pack(Y)
+    assert d == d2 and sigma > 0
+    nx, ny = len(xo) - 1, len(yo) - 1
+    if not gram:
+        assert nx == ny
+    out = np.empty((nx, ny) if gram else (nx,), dtype=np.float64)
+    _load().sko_lifted_rbf_batch(_dptr(xf), _iptr(xo), nx, _dptr(yf), _iptr(yo), ny, d,
+                                 int(dyadic_order), float(sigma),
+                                 1 if scheme == "implicit" else 0, 1 if gram else 0,
+                                 _dptr(out), int(nthreads))
+    return out
+
+
+def lifted_rbf_pairs(xs, ys, dyadic_order: int = 0, sigma: float = 1.0,
+                     scheme: str = "explicit", nthreads: int = 0) -> np.ndarray:
+    """RBF-lifted kernels of independent pairs (OpenMP over pairs)."""
+    return _lifted_rbf_batch(xs, ys, dyadic_order, sigma, scheme, False, nthreads)
+
+
+def lifted_rbf_gram(X, Y, dyadic_order: int = 0, sigma: float = 1.0,
+                    scheme: str = "explicit", nthreads: int = 0) -> np.ndarray:
+    """RBF-lifted Gram matrix K[a, b] = k(X_a, Y_b) (OpenMP over pairs)."""
+    return _lifted_rbf_batch(X, Y, dyadic_order, sigma, scheme, True, nthreads)

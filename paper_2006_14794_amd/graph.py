@@ -68,29 +68,30 @@ def _buffers(op: int, X, Y, dyadic_order: int, flags: int, n_out):
 
 
 def capture_gram(X, Y=None, dyadic_order: int = 0, *, symmetric: bool = False,
-                 no_diag: bool = False, gram_precision: str = "f32"):
+                 no_diag: bool = False, gram_precision: str = "f32", scheme: str = "explicit"):
     """(graph, K): sigkernel_gram captured once; each ``graph.replay()``
     recomputes K in place from the current contents of X and Y."""
-    from .api import _device, _gram_flag, _n_paths, sigkernel_gram
+    from .api import _device, _gram_flag, _n_paths, _scheme_flag, sigkernel_gram
     Yv = X if Y is None else Y
-    flags = _gram_flag(gram_precision)
+    flags = _gram_flag(gram_precision) | _scheme_flag(scheme)
     if symmetric:
         flags |= _lib.SK_SYMMETRIC | (_lib.SK_NO_DIAG if no_diag else 0)
     K, ws = _buffers(_lib.SK_OP_GRAM, X, Yv, dyadic_order, flags, (_n_paths(X), _n_paths(Yv)))
     g = CapturedCalls(lambda: sigkernel_gram(X, Y, dyadic_order, symmetric=symmetric,
                                              no_diag=no_diag, gram_precision=gram_precision,
-                                             out=K, workspace=ws), _device(X))
+                                             scheme=scheme, out=K, workspace=ws), _device(X))
     g._keep = (ws,)
     return g, K
 
 
-def capture_pair(x, y, dyadic_order: int = 0, *, gram_precision: str = "f32"):
+def capture_pair(x, y, dyadic_order: int = 0, *, gram_precision: str = "f32",
+                 scheme: str = "explicit"):
     """(graph, out): sigkernel_pair captured once (independent pairs)."""
-    from .api import _device, _gram_flag, _n_paths, sigkernel_pair
-    flags = _gram_flag(gram_precision)
+    from .api import _device, _gram_flag, _n_paths, _scheme_flag, sigkernel_pair
+    flags = _gram_flag(gram_precision) | _scheme_flag(scheme)
     out, ws = _buffers(_lib.SK_OP_PAIR, x, y, dyadic_order, flags, (_n_paths(x),))
     g = CapturedCalls(lambda: sigkernel_pair(x, y, dyadic_order, gram_precision=gram_precision,
-                                             out=out, workspace=ws), _device(x))
+                                             scheme=scheme, out=out, workspace=ws), _device(x))
     g._keep = (ws,)
     return g, out
 

@@ -91,21 +91,22 @@ def tune_clear() -> None:
 
 
 def autotune(op, X, Y=None, dyadic_order: int = 0, *, symmetric: bool = False,
-             no_diag: bool = False, gram_precision: str = "f32", reps: int = 3,
-             cache: Optional[str] = None) -> Tuple[Dict[str, int], float]:
+             no_diag: bool = False, gram_precision: str = "f32", scheme: str = "explicit",
+             reps: int = 3, cache: Optional[str] = None) -> Tuple[Dict[str, int], float]:
     """Time the candidate tunings of a forward call ('pair' or 'gram') on the
     current stream, keep the fastest in the table and return (tuning, ms).
     With ``cache`` the whole table is then written to that JSON file."""
     import torch
 
-    from .api import _describe, _device, _gram_flag, _n_paths, _stream_ptr, workspace_bytes
+    from .api import (_describe, _device, _gram_flag, _n_paths, _scheme_flag, _stream_ptr,
+                      workspace_bytes)
     lib = _lib.load()
     opn = _op(op)
     if opn not in (_lib.SK_OP_PAIR, _lib.SK_OP_GRAM):
         raise ValueError("autotune covers the forward calls 'pair' and 'gram'")
     if Y is None:
         Y = X
-    flags = _gram_flag(gram_precision)
+    flags = _gram_flag(gram_precision) | _scheme_flag(scheme)
     if symmetric:
         flags |= _lib.SK_SYMMETRIC | (_lib.SK_NO_DIAG if no_diag else 0)
     dev = _device(X)
