@@ -51,8 +51,10 @@ enum {
     SK_ERR_FLAGS = -5,       /* unknown or incompatible flag bits                   */
     SK_ERR_HIP = -6,         /* a HIP launch failed                                 */
     SK_ERR_UNSUPPORTED = -7, /* shape outside the compiled kernel configurations    */
-    SK_ERR_STATE = -8        /* not allowed in the stream's current state (a call
+    SK_ERR_STATE = -8,       /* not allowed in the stream's current state (a call
                                 that synchronises, issued under graph capture)      */
+    SK_ERR_VALUE = -9        /* a parameter outside its domain (an unknown static
+                                kernel, a bandwidth that is not positive and finite) */
 };
 
 /*
@@ -173,11 +175,62 @@ sk_status sigkernel_mmd2(const sk_paths *X, const sk_paths *Y, int32_t dyadic_or
                          uint32_t flags, float *mmd2, float *dX, void *ws, size_t ws_bytes,
                          void *stream);
 
+/*
+ * Signature kernels of lifted paths (the static-kernel lift, eq. (PDE_lifted)
+ * and the finite-difference form that follows it).  A static kernel kappa on
+ * R^d lifts x and y to paths X = phi(x), Y = psi(y) in a feature space; the
+ * PDE for their signature kernel has, on the coarse cell between nodes p, p+1
+ * of x and q, q+1 of y, the coefficient
+ *   G[p][q] = kappa(x_{p+1}, y_{q+1}) - kappa(x_p, y_{q+1})
+ *             - kappa(x_{p+1}, y_q) + kappa(x_p, y_q)
+ * (the printed second term reads kappa(x_{s-1}, x_t); the pairing of X with Y
+ * makes it kappa(x_{s-1}, y_t)), which replaces <dx_p, dy_q> in the scheme on
+ * P_lambda (explicit, or implicit with SK_IMPLICIT).  Static kernels:
+ *   SK_STATIC_LINEAR  kappa(a, b) = <a, b>: its lift is the path itself, and
+ *                     the calls run the plain scheme (sigkernel_pair / _gram,
+ *                     whose flags they then accept);
+ *   SK_STATIC_RBF     kappa(a, b) = exp(-|a - b|^2 / (2 sigma^2)), sigma > 0
+ *                     (the RBF-lifted kernel of the paper's experiments,
+ *                     Section 5).  kappa and G are formed in double from the
+ *                     float32 points (their coordinate differences are exact
+ *                     in double), the sweep state is double, outputs float32.
+ */
+enum { SK_STATIC_LINEAR = 0, SK_STATIC_RBF = 1 };
+typedef struct sk_static_kernel {
+    int32_t kind;      /* SK_STATIC_LINEAR or SK_STATIC_RBF                     */
+    int32_t reserved;  /* 0                                                     */
+    double sigma;      /* SK_STATIC_RBF: the bandwidth (> 0, finite)            */
+} sk_static_kernel;
+
+/*
+ * sigkernel_pair_lifted / sigkernel_gram_lifted -- as sigkernel_pair /
+ * sigkernel_gram (same batches, outputs, modes and errors) for the lifted
+ * kernel of `kernel` (HOST pointer, read during the call only).
+ *  - flags: SK_IMPLICIT; the Gram also SK_SYMMETRIC / SK_NO_DIAG.  The 16-bit
+ *    increment flags only with SK_STATIC_LINEAR.
+ *  - SK_STATIC_RBF: the x paths must fit one wave's rows (2^lambda (x.len - 1)
+ *    fine rows within the compiled rows-per-lane limits, at most 2048);
+ *    taller x paths give SK_ERR_UNSUPPORTED (swap the arguments: the kernel
+ *    is symmetric in the pair).  No gradient.
+ *  - Workspace: sigkernel_workspace_bytes(SK_OP_PAIR_LIFTED / SK_OP_GRAM_LIFTED,
+ *    ...), enough for either static kernel.
+ *  - SK_ERR_VALUE: unknown kind, or sigma not positive and finite (or so small
+ *    that 1 / (2 sigma^2) overflows).
+ */
+sk_status sigkernel_pair_lifted(const sk_paths *x, const sk_paths *y, int32_t dyadic_order,
+                                uint32_t flags, const sk_static_kernel *kernel, float *out,
+                                void *ws, size_t ws_bytes, void *stream);
+sk_status sigkernel_gram_lifted(const sk_paths *X, const sk_paths *Y, int32_t dyadic_order,
+                                uint32_t flags, const sk_static_kernel *kernel, float *K,
+                                void *ws, size_t ws_bytes, void *stream);
+
 /* Workspace sizing.  op is one of the SK_OP_* values. */
 enum { SK_OP_PAIR = 0, SK_OP_GRAM = 1, SK_OP_GRAM_BACKWARD = 2, SK_OP_MMD2 = 3,
        SK_OP_CORRECTOR_FEATURES = 4,  /* X, Y: the pairs                              */
        SK_OP_CORRECTOR_BACKWARD = 5,  /* X->n_paths: the batch size (Y unused)        */
-       SK_OP_CORRECTOR_PREDICT = 6    /* X, Y: the pairs; dyadic_order: the fallback  */
+       SK_OP_CORRECTOR_PREDICT = 6,   /* X, Y: the pairs; dyadic_order: the fallback  */
+       SK_OP_PAIR_LIFTED = 7,         /* sigkernel_pair_lifted                        */
+       SK_OP_GRAM_LIFTED = 8          /* sigkernel_gram_lifted                        */
 };
 size_t sigkernel_workspace_bytes(int32_t op, const sk_paths *X, const sk_paths *Y,
                                  int32_t dyadic_order, uint32_t flags);

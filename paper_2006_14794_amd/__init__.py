@@ -10,7 +10,7 @@ is the thin Python binding; it never computes anything on the CPU.
 from ._lib import SK_NO_DIAG, SK_SYMMETRIC, SigKernelError, load, status_string, version
 from .api import (RaggedPaths, SigKernelGram, SigKernelGramSymmetric, SigKernelMMD2, gram, mmd2,
                   sigkernel_gram, sigkernel_gram_backward, sigkernel_increment_gram, sigkernel_mmd2,
-                  sigkernel_pair,
+                  sigkernel_gram_lifted, sigkernel_pair, sigkernel_pair_lifted,
                   workspace_bytes)
 from . import corrector
 from .corrector import Corrector
@@ -21,6 +21,7 @@ __all__ = [
     "RaggedPaths", "SigKernelError", "SigKernelGram", "SigKernelGramSymmetric", "gram", "load",
     "SigKernelMMD2", "mmd2", "sigkernel_mmd2", "sigkernel_increment_gram",
     "sigkernel_gram", "sigkernel_gram_backward", "sigkernel_pair",
+    "sigkernel_gram_lifted", "sigkernel_pair_lifted",
     "status_string", "version", "workspace_bytes",
     "SK_SYMMETRIC", "SK_NO_DIAG",
     "Corrector", "corrector",

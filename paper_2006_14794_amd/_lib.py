@@ -22,6 +22,7 @@ SK_ERR_FLAGS = -5
 SK_ERR_HIP = -6
 SK_ERR_UNSUPPORTED = -7
 SK_ERR_STATE = -8
+SK_ERR_VALUE = -9
 
 SK_SYMMETRIC = 1 << 0
 SK_NO_DIAG = 1 << 1
@@ -37,6 +38,11 @@ SK_OP_MMD2 = 3
 SK_OP_CORRECTOR_FEATURES = 4
 SK_OP_CORRECTOR_BACKWARD = 5
 SK_OP_CORRECTOR_PREDICT = 6
+SK_OP_PAIR_LIFTED = 7
+SK_OP_GRAM_LIFTED = 8
+
+SK_STATIC_LINEAR = 0
+SK_STATIC_RBF = 1
 SK_CHANNEL_STATS_WORKSPACE_BYTES = 32832
 
 # Every symbol the header declares (checked by the CPU test suite).
@@ -68,6 +74,8 @@ EXPORTED = (
     "sigkernel_adam_step",
     "sigkernel_channel_stats",
     "sigkernel_corrector_predict",
+    "sigkernel_pair_lifted",
+    "sigkernel_gram_lifted",
 )
 
 
@@ -78,6 +86,14 @@ class SkPaths(ctypes.Structure):
         ("n_paths", ctypes.c_int64),
         ("len", ctypes.c_int32),
         ("dim", ctypes.c_int32),
+    ]
+
+
+class SkStaticKernel(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("sigma", ctypes.c_double),
     ]
 
 
@@ -131,6 +147,10 @@ def load():
     lib.sigkernel_pair.restype = i32
     lib.sigkernel_gram.argtypes = [P, P, i32, u32, vp, vp, sz, vp]
     lib.sigkernel_gram.restype = i32
+    SKp = ctypes.POINTER(SkStaticKernel)
+    for name in ("sigkernel_pair_lifted", "sigkernel_gram_lifted"):
+        getattr(lib, name).argtypes = [P, P, i32, u32, SKp, vp, vp, sz, vp]
+        getattr(lib, name).restype = i32
     lib.sigkernel_gram_backward.argtypes = [P, P, i32, u32, vp, vp, vp, vp, sz, vp]
     lib.sigkernel_gram_backward.restype = i32
     lib.sigkernel_mmd2.argtypes = [P, P, i32, u32, vp, vp, vp, sz, vp]

@@ -171,6 +171,78 @@ def sigkernel_gram(X: PathsLike, Y: Optional[PathsLike] = None, dyadic_order: in
     return out
 
 
+def _static_kernel(kernel: str, sigma: float):
+    if kernel == "rbf":
+        if not (sigma > 0):
+            raise ValueError("the RBF bandwidth sigma must be positive")
+        return _lib.SkStaticKernel(_lib.SK_STATIC_RBF, 0, float(sigma))
+    if kernel == "linear":
+        return _lib.SkStaticKernel(_lib.SK_STATIC_LINEAR, 0, 0.0)
+    raise ValueError("kernel must be 'rbf' or 'linear'")
+
+
+def sigkernel_pair_lifted(x: PathsLike, y: PathsLike, dyadic_order: int = 0, *,
+                          kernel: str = "rbf", sigma: float = 1.0, scheme: str = "explicit",
+                          out: Optional[torch.Tensor] = None,
+                          workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """out[k] = signature kernel of the lifted pair (x_k, y_k): the scheme on
+    P_lambda with the coarse coefficients replaced by second differences of
+    the static kernel ('rbf': exp(-|a - b|^2 / (2 sigma^2)); 'linear': the
+    plain kernel)."""
+    lib = _lib.load()
+    dev = _device(x)
+    n = _n_paths(x)
+    flags = _scheme_flag(scheme)
+    sk_ = _static_kernel(kernel, sigma)
+    sx, sy = _describe(x), _describe(y)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=dev)
+    nbytes = int(lib.sigkernel_workspace_bytes(_lib.SK_OP_PAIR_LIFTED, ctypes.byref(sx),
+                                               ctypes.byref(sy), dyadic_order, flags))
+    ws = _workspace(nbytes, dev, workspace)
+    st = lib.sigkernel_pair_lifted(ctypes.byref(sx), ctypes.byref(sy), int(dyadic_order), flags,
+                                   ctypes.byref(sk_), out.data_ptr() if n else None,
+                                   ws.data_ptr(), ws.numel() * ws.element_size(),
+                                   _stream_ptr(dev))
+    _lib.check(st, "sigkernel_pair_lifted")
+    return out
+
+
+def sigkernel_gram_lifted(X: PathsLike, Y: Optional[PathsLike] = None, dyadic_order: int = 0,
+                          *, kernel: str = "rbf", sigma: float = 1.0, symmetric: bool = False,
+                          no_diag: bool = False, scheme: str = "explicit",
+                          out: Optional[torch.Tensor] = None,
+                          workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """K[a, b] = lifted signature kernel of (X_a, Y_b) (see
+    ``sigkernel_pair_lifted``); ``symmetric`` / ``no_diag`` as in
+    ``sigkernel_gram``."""
+    lib = _lib.load()
+    if Y is None:
+        Y = X
+    if symmetric and Y is not X:
+        raise ValueError("symmetric Gram needs Y to be X")
+    if no_diag and not symmetric:
+        raise ValueError("no_diag needs symmetric=True")
+    dev = _device(X)
+    nx, ny = _n_paths(X), _n_paths(Y)
+    flags = _scheme_flag(scheme)
+    if symmetric:
+        flags |= _lib.SK_SYMMETRIC | (_lib.SK_NO_DIAG if no_diag else 0)
+    sk_ = _static_kernel(kernel, sigma)
+    sx, sy = _describe(X), _describe(Y)
+    if out is None:
+        out = torch.empty((nx, ny), dtype=torch.float32, device=dev)
+    nbytes = int(lib.sigkernel_workspace_bytes(_lib.SK_OP_GRAM_LIFTED, ctypes.byref(sx),
+                                               ctypes.byref(sy), dyadic_order, flags))
+    ws = _workspace(nbytes, dev, workspace)
+    st = lib.sigkernel_gram_lifted(ctypes.byref(sx), ctypes.byref(sy), int(dyadic_order), flags,
+                                   ctypes.byref(sk_), out.data_ptr() if out.numel() else None,
+                                   ws.data_ptr(), ws.numel() * ws.element_size(),
+                                   _stream_ptr(dev))
+    _lib.check(st, "sigkernel_gram_lifted")
+    return out
+
+
 def sigkernel_gram_backward(X: torch.Tensor, Y: Optional[torch.Tensor], dK: torch.Tensor,
                             dyadic_order: int = 0, *, symmetric: bool = False,
                             no_diag: bool = False, need_x: bool = True, need_y: bool = True,

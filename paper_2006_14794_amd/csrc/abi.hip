@@ -470,6 +470,107 @@ sk_status corrector_forward(const float* params, const sk::corr::bf16* feats, in
   return SK_OK;
 }
 
+// ---- static-kernel lift ------------------------------------------------------
+// Workspace of the lifted sweep: dense node rows of X and of Y (kStreamPad
+// rows on each side), then the ragged plans.
+struct LiftedLayout {
+  size_t nodex, nodey, planx_n, planx_start, plany_n, plany_start, total;
+};
+
+size_t node_rows(const sk_paths* p) {
+  return (size_t)p->n_paths * (size_t)p->len + 2 * (size_t)sk::kStreamPad;
+}
+
+LiftedLayout lifted_layout(const sk_paths* X, const sk_paths* Y) {
+  const size_t dp = (size_t)sk::padded_dim(X->dim);
+  LiftedLayout L{};
+  size_t off = 0;
+  L.nodex = off;
+  off += align256(node_rows(X) * dp * sizeof(float));
+  L.nodey = off;
+  off += align256(node_rows(Y) * dp * sizeof(float));
+  L.planx_n = off;
+  off += plan_bytes_n(X);
+  L.planx_start = off;
+  off += plan_bytes_start(X);
+  L.plany_n = off;
+  off += plan_bytes_n(Y);
+  L.plany_start = off;
+  off += plan_bytes_start(Y);
+  L.total = off;
+  return L;
+}
+
+sk_status check_static_kernel(const sk_static_kernel* k) {
+  if (!k) return SK_ERR_NULL;
+  if (k->kind == SK_STATIC_LINEAR) return SK_OK;
+  if (k->kind != SK_STATIC_RBF) return SK_ERR_VALUE;
+  return (k->sigma > 0.0 && isfinite(k->sigma) && isfinite(1.0 / (2.0 * k->sigma * k->sigma)))
+             ? SK_OK
+             : SK_ERR_VALUE;
+}
+
+// mode 0: pairs (x_k, y_k); 1: Gram; 2: symmetric Gram (upper triangle, mirrored)
+sk_status run_lifted(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t flags,
+                     const sk_static_kernel* kernel, float* out, void* ws, size_t ws_bytes,
+                     hipStream_t stream, int mode) {
+  // the linear kernel's lift is the path itself: the plain scheme
+  if (kernel->kind == SK_STATIC_LINEAR)
+    return run_forward(X, Y, lam, flags, out, ws, ws_bytes, stream, mode);
+  const int d = X->dim;
+  const int dp = sk::padded_dim(d);
+  const int64_t fine_rows = (int64_t)(X->len - 1) << lam;
+  const int R = sk::choose_rows_for(sk::kKernelLifted, fine_rows < 1 ? 1 : fine_rows, lam, d);
+  if (R == 0) return SK_ERR_UNSUPPORTED;
+  const LiftedLayout L = lifted_layout(X, Y);
+  if (ws_bytes < L.total) return SK_ERR_WORKSPACE;
+  char* base = static_cast<char*>(ws);
+  float* nx = reinterpret_cast<float*>(base + L.nodex) + sk::kStreamPad * dp;
+  float* ny = reinterpret_cast<float*>(base + L.nodey) + sk::kStreamPad * dp;
+  sk::PathPlan px{reinterpret_cast<int32_t*>(base + L.planx_n),
+                  reinterpret_cast<int64_t*>(base + L.planx_start)};
+  sk::PathPlan py{reinterpret_cast<int32_t*>(base + L.plany_n),
+                  reinterpret_cast<int64_t*>(base + L.plany_start)};
+  const sk::Batch bx = to_batch(X), by = to_batch(Y);
+  if (X->offsets && sk::launch_plan(bx, px, stream) != hipSuccess) return SK_ERR_HIP;
+  if (Y->offsets && sk::launch_plan(by, py, stream) != hipSuccess) return SK_ERR_HIP;
+  if (sk::launch_nodes(bx, X->offsets ? &px : nullptr, dp, nx, stream) != hipSuccess)
+    return SK_ERR_HIP;
+  if (sk::launch_nodes(by, Y->offsets ? &py : nullptr, dp, ny, stream) != hipSuccess)
+    return SK_ERR_HIP;
+
+  sk::SweepArgs a{};
+  a.incx = nx;
+  a.incy = ny;
+  a.x_n = X->offsets ? px.n : nullptr;
+  a.x_start = X->offsets ? px.start : nullptr;
+  a.y_n = Y->offsets ? py.n : nullptr;
+  a.y_start = Y->offsets ? py.start : nullptr;
+  a.x_len = X->len;
+  a.y_len = Y->len;
+  a.nx = X->n_paths;
+  a.ny = Y->n_paths;
+  a.mode = mode;
+  a.no_diag = (flags & SK_NO_DIAG) ? 1 : 0;
+  a.implicit = (flags & SK_IMPLICIT) ? 1 : 0;
+  a.lift_inv = 1.0 / (2.0 * kernel->sigma * kernel->sigma);
+  a.lift_scale = ldexp(1.0, -(2 * lam + 1));
+  a.out = out;
+  a.out_ld = Y->n_paths;
+  if (mode == 0) {
+    a.run = 1;
+    a.runs_per_row = 1;
+    a.n_waves = X->n_paths;
+  } else {
+    a.run = Y->offsets ? 1 : (int32_t)choose_run(X->n_paths, Y->n_paths, 0);
+    a.runs_per_row = (Y->n_paths + a.run - 1) / a.run;
+    a.n_waves = X->n_paths * a.runs_per_row;
+  }
+  const hipError_t e = sk::launch_lifted(a, lam, R, d, stream, 0);
+  if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;
+  return e == hipSuccess ? SK_OK : SK_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -487,6 +588,7 @@ const char* sigkernel_status_string(sk_status s) {
     case SK_ERR_HIP: return "HIP launch error";
     case SK_ERR_UNSUPPORTED: return "shape outside the compiled configurations";
     case SK_ERR_STATE: return "not allowed while the stream is being captured";
+    case SK_ERR_VALUE: return "parameter outside its domain";
     default: return "unknown status";
   }
 }
@@ -520,6 +622,14 @@ size_t sigkernel_workspace_bytes(int32_t op, const sk_paths* X, const sk_paths* 
     case SK_OP_CORRECTOR_PREDICT:
       if (check_corrector_batches(X, Y) == SK_ERR_SHAPE) return 0;
       return predict_layout(X, Y, dyadic_order).total;
+    case SK_OP_PAIR_LIFTED:
+    case SK_OP_GRAM_LIFTED: {
+      // the linear static kernel runs the plain calls: room for either
+      const size_t f = lifted_layout(X, Y).total;
+      const size_t g = sigkernel_workspace_bytes(op == SK_OP_PAIR_LIFTED ? SK_OP_PAIR : SK_OP_GRAM,
+                                                 X, Y, dyadic_order, flags);
+      return f > g ? f : g;
+    }
     default:
       return 0;
   }
@@ -559,6 +669,50 @@ sk_status sigkernel_gram(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
   if (!ws) return SK_ERR_WORKSPACE;
   return run_forward(X, Y, dyadic_order, flags, K, ws, ws_bytes,
                      static_cast<hipStream_t>(stream), (flags & SK_SYMMETRIC) ? 2 : 1);
+}
+
+sk_status sigkernel_pair_lifted(const sk_paths* x, const sk_paths* y, int32_t dyadic_order,
+                                uint32_t flags, const sk_static_kernel* kernel, float* out,
+                                void* ws, size_t ws_bytes, void* stream) {
+  if (!x || !y) return SK_ERR_NULL;
+  if (!valid_batch(x) || !valid_batch(y)) return SK_ERR_SHAPE;
+  if (!out && x->n_paths > 0) return SK_ERR_NULL;
+  if ((x->n_paths > 0 && !x->points) || (y->n_paths > 0 && !y->points)) return SK_ERR_NULL;
+  if (x->dim != y->dim || x->n_paths != y->n_paths) return SK_ERR_SHAPE;
+  if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (sk_status k = check_static_kernel(kernel)) return k;
+  const uint32_t allowed = kernel->kind == SK_STATIC_LINEAR ? SK_IMPLICIT | SK_GRAM_BF16 |
+                                                                  SK_GRAM_F16
+                                                            : SK_IMPLICIT;
+  if (sk_status f = check_flags(flags, allowed)) return f;
+  if (x->n_paths == 0) return SK_OK;
+  if (!ws) return SK_ERR_WORKSPACE;
+  return run_lifted(x, y, dyadic_order, flags, kernel, out, ws, ws_bytes,
+                    static_cast<hipStream_t>(stream), 0);
+}
+
+sk_status sigkernel_gram_lifted(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
+                                uint32_t flags, const sk_static_kernel* kernel, float* K,
+                                void* ws, size_t ws_bytes, void* stream) {
+  if (!X || !Y) return SK_ERR_NULL;
+  if (!valid_batch(X) || !valid_batch(Y)) return SK_ERR_SHAPE;
+  if (!K && X->n_paths > 0 && Y->n_paths > 0) return SK_ERR_NULL;
+  if ((X->n_paths > 0 && !X->points) || (Y->n_paths > 0 && !Y->points)) return SK_ERR_NULL;
+  if (X->dim != Y->dim) return SK_ERR_SHAPE;
+  if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (sk_status k = check_static_kernel(kernel)) return k;
+  const uint32_t allowed =
+      SK_SYMMETRIC | SK_NO_DIAG | SK_IMPLICIT |
+      (kernel->kind == SK_STATIC_LINEAR ? SK_GRAM_BF16 | SK_GRAM_F16 : 0u);
+  if (sk_status f = check_flags(flags, allowed)) return f;
+  if ((flags & SK_SYMMETRIC) &&
+      (X->points != Y->points || X->offsets != Y->offsets || X->n_paths != Y->n_paths ||
+       X->len != Y->len))
+    return SK_ERR_SHAPE;
+  if (X->n_paths == 0 || Y->n_paths == 0) return SK_OK;
+  if (!ws) return SK_ERR_WORKSPACE;
+  return run_lifted(X, Y, dyadic_order, flags, kernel, K, ws, ws_bytes,
+                    static_cast<hipStream_t>(stream), (flags & SK_SYMMETRIC) ? 2 : 1);
 }
 
 sk_status sigkernel_increment_gram(const sk_paths* X, const sk_paths* Y, int32_t gram,

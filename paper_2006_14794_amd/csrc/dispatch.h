@@ -18,6 +18,12 @@ constexpr bool adjoint_fits(int R, int LAM, int D) {
   return ((R >> LAM) > 0 ? (R >> LAM) : 1) * D <= 72 && R <= 16;
 }
 
+// The lifted sweep keeps the x nodes (coarse rows + 1) instead of the
+// increments, plus the previous column's row differences.
+constexpr bool lifted_fits(int R, int LAM, int D) {
+  return (((R >> LAM) > 0 ? (R >> LAM) : 1) + 1) * D <= 96 && R <= 32;
+}
+
 template <class F, int R, int LAM>
 typename F::Fn pick_d(int d) {
   switch (d) {

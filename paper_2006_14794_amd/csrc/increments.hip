@@ -89,6 +89,34 @@ __global__ __launch_bounds__(256) void increments_kernel(
   }
 }
 
+// One workgroup per path: its points as dense padded rows [start + k, start
+// + k + n + 1) (uniform: [k len, (k + 1) len)), channels beyond d zero.
+__global__ __launch_bounds__(256) void nodes_kernel(
+    const float* __restrict__ pts, const int64_t* __restrict__ off,
+    const int32_t* __restrict__ plan_n, const int64_t* __restrict__ plan_start, int32_t len,
+    int64_t n_paths, int32_t d, int32_t dpad, float* __restrict__ nodes) {
+  const int64_t k = blockIdx.x;
+  if (k >= n_paths) return;
+  int64_t pstart, dstart;
+  int32_t n;
+  if (off) {
+    n = plan_n[k];
+    if (n < 0) return;
+    pstart = off[k];
+    dstart = plan_start[k] + k;
+  } else {
+    n = len - 1;
+    pstart = k * (int64_t)len;
+    dstart = k * (int64_t)len;
+  }
+  const int64_t total = (int64_t)(n + 1) * dpad;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int64_t p = e / dpad;
+    const int c = (int)(e - p * dpad);
+    nodes[(dstart + p) * dpad + c] = c < d ? pts[(pstart + p) * d + c] : 0.0f;
+  }
+}
+
 __global__ __launch_bounds__(256) void fill_kernel(float* __restrict__ p, int64_t n, float v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -119,6 +147,15 @@ hipError_t launch_increments(const Batch& b, const PathPlan* plan, float scale, 
                      b.points, b.offsets, plan ? plan->n : nullptr,
                      plan ? plan->start : nullptr, b.len, b.n_paths, b.dim, dpad, scale,
                      rounding, incr);
+  return hipGetLastError();
+}
+
+hipError_t launch_nodes(const Batch& b, const PathPlan* plan, int dpad, float* nodes,
+                        hipStream_t stream) {
+  if (b.n_paths == 0) return hipSuccess;
+  hipLaunchKernelGGL(nodes_kernel, dim3((unsigned)b.n_paths), dim3(256), 0, stream, b.points,
+                     b.offsets, plan ? plan->n : nullptr, plan ? plan->start : nullptr, b.len,
+                     b.n_paths, b.dim, dpad, nodes);
   return hipGetLastError();
 }
 

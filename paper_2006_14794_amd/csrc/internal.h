@@ -44,10 +44,18 @@ enum { kRoundNone = 0, kRoundBf16 = 1, kRoundF16 = 2 };
 hipError_t launch_increments(const Batch& b, const PathPlan* plan, float scale, int dpad,
                              float* incr, hipStream_t stream, int rounding = kRoundNone);
 
+// Dense padded node rows (the points themselves): path k occupies rows
+// [start[k] + k, start[k] + k + n[k] + 1) of a ragged batch, [k len, (k + 1)
+// len) of a uniform one; channels beyond d are zero.  Paths with n[k] < 0 are
+// skipped.
+hipError_t launch_nodes(const Batch& b, const PathPlan* plan, int dpad, float* nodes,
+                        hipStream_t stream);
+
 // Work description of one forward sweep launch.
 struct SweepArgs {
   const float* incx;        // dense increments of the x side, pre-scaled by 2^-(2 lam + 1)
-  const float* incy;        // dense increments of the y side
+                            // (lifted sweep: dense node rows of x, not scaled)
+  const float* incy;        // dense increments of the y side (lifted sweep: node rows of y)
   const int32_t* x_n;       // ragged plans (nullptr for a uniform batch)
   const int64_t* x_start;
   const int32_t* y_n;
@@ -57,6 +65,8 @@ struct SweepArgs {
   int32_t mode;             // 0: pairs (x_k, y_k); 1: Gram; 2: Gram upper triangle, mirrored
   int32_t no_diag;          // mode 2: diagonal written as 0
   int32_t implicit;         // 1: the implicit scheme's cell factor (2 + h) / (2 - h)
+  double lift_inv;          // lifted sweep: 1 / (2 sigma^2) of the Gaussian static kernel
+  double lift_scale;        // lifted sweep: 2^-(2 lam + 1), the coefficient's fine-cell factor
   int32_t run;              // pairs streamed through one wave (Gram with uniform y)
   int64_t runs_per_row;     // ceil(ny / run)
   int64_t n_waves;
@@ -87,6 +97,13 @@ hipError_t launch_sweep(const SweepArgs& a, int lam, int rows_per_lane, int dim,
                         hipStream_t stream, int waves_per_block = 0);
 hipError_t launch_sweep_store(const SweepArgs& a, int lam, int rows_per_lane, int dim,
                               hipStream_t stream, int waves_per_block = 0);
+// The sweep of the Gaussian-lifted kernel (lifted_kernel.h): incx / incy hold
+// node rows, lift_inv and lift_scale are set.
+hipError_t launch_lifted(const SweepArgs& a, int lam, int rows_per_lane, int dim,
+                         hipStream_t stream, int waves_per_block = 0);
+// Rows per lane of a compiled sweep kernel of the given kind for `fine_rows`
+// rows (0 if none).
+int choose_rows_for(int kind, int64_t fine_rows, int lam, int dim);
 
 // Adjoint sweep of a Gram batch (uniform batches).
 struct BwdArgs {
@@ -173,7 +190,8 @@ hipError_t launch_gram_mfma(const GramArgs& a, int precision, hipStream_t stream
 
 // Compiled sweep kernels by kind, dyadic order, rows per lane and channels
 // (nullptr when the configuration is not compiled).
-enum { kKernelForward = 0, kKernelForwardStore = 1, kKernelAdjoint = 2, kKernelPair = 3 };
+enum { kKernelForward = 0, kKernelForwardStore = 1, kKernelAdjoint = 2, kKernelPair = 3,
+       kKernelLifted = 4 };
 void* sweep_fn(int kind, int lam, int rows_per_lane, int dim);
 
 // Steps of a wave that streams `total` coarse columns (a multiple of three:

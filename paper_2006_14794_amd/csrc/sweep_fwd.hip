@@ -9,25 +9,31 @@ SK_DECL(0, 0) SK_DECL(0, 1) SK_DECL(0, 2) SK_DECL(0, 3)
 SK_DECL(1, 0) SK_DECL(1, 1) SK_DECL(1, 2) SK_DECL(1, 3)
 SK_DECL(2, 0) SK_DECL(2, 1) SK_DECL(2, 2) SK_DECL(2, 3)
 SK_DECL(3, 0) SK_DECL(3, 1) SK_DECL(3, 2) SK_DECL(3, 3)
+SK_DECL(4, 0) SK_DECL(4, 1) SK_DECL(4, 2) SK_DECL(4, 3)
 #undef SK_DECL
 
 void* sweep_fn(int kind, int lam, int R, int d) {
   using Pick = void* (*)(int, int);
-  static const Pick table[4][4] = {
+  static const Pick table[5][4] = {
       {sweep_fn_k0_l0_, sweep_fn_k0_l1_, sweep_fn_k0_l2_, sweep_fn_k0_l3_},
       {sweep_fn_k1_l0_, sweep_fn_k1_l1_, sweep_fn_k1_l2_, sweep_fn_k1_l3_},
       {sweep_fn_k2_l0_, sweep_fn_k2_l1_, sweep_fn_k2_l2_, sweep_fn_k2_l3_},
-      {sweep_fn_k3_l0_, sweep_fn_k3_l1_, sweep_fn_k3_l2_, sweep_fn_k3_l3_}};
-  if (kind < 0 || kind > 3 || lam < 0 || lam > 3) return nullptr;
+      {sweep_fn_k3_l0_, sweep_fn_k3_l1_, sweep_fn_k3_l2_, sweep_fn_k3_l3_},
+      {sweep_fn_k4_l0_, sweep_fn_k4_l1_, sweep_fn_k4_l2_, sweep_fn_k4_l3_}};
+  if (kind < 0 || kind > 4 || lam < 0 || lam > 3) return nullptr;
   return table[kind][lam](R, d);
 }
 
-int choose_rows_per_lane(int64_t fine_rows, int lam, int d) {
+int choose_rows_for(int kind, int64_t fine_rows, int lam, int d) {
   for (int R = 1; R <= kMaxRowsPerLane; R *= 2) {
     if (64 * (int64_t)R < fine_rows) continue;
-    return sweep_fn(kKernelForward, lam, R, d) ? R : 0;
+    return sweep_fn(kind, lam, R, d) ? R : 0;
   }
   return 0;
+}
+
+int choose_rows_per_lane(int64_t fine_rows, int lam, int d) {
+  return choose_rows_for(kKernelForward, fine_rows, lam, d);
 }
 
 namespace {
@@ -46,6 +52,11 @@ hipError_t launch_forward(int kind, const SweepArgs& a, int lam, int R, int d,
 hipError_t launch_sweep(const SweepArgs& a, int lam, int R, int d, hipStream_t stream,
                         int waves_per_block) {
   return launch_forward(kKernelForward, a, lam, R, d, stream, waves_per_block);
+}
+
+hipError_t launch_lifted(const SweepArgs& a, int lam, int R, int d, hipStream_t stream,
+                         int waves_per_block) {
+  return launch_forward(kKernelLifted, a, lam, R, d, stream, waves_per_block);
 }
 
 hipError_t launch_sweep_store(const SweepArgs& a, int lam, int R, int d, hipStream_t stream,

@@ -93,18 +93,15 @@ __device__ __forceinline__ void store_cells(float* __restrict__ p, const float (
   }
 }
 
-template <int R, int LAM, int D, bool STORE>
-__global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
-  constexpr int DP = (D + 3) & ~3;
-  constexpr int S = 1 << LAM;                          // fine columns per coarse column
-  constexpr int CR = (R >> LAM) > 0 ? (R >> LAM) : 1;  // coarse rows per lane
-
-  const int lane = threadIdx.x & 63;
-  const int64_t w = a.wave0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (w >= a.wave0 + a.n_waves) return;  // uniform per wave
-
-  // ---- the run of pairs of this wave -------------------------------------
-  int64_t ia, b0, b1;
+// Resolves the run of pairs (x_ia, y_b), b in [b0, b1), of wave w, writes the
+// value of every pair with nothing to sweep (a broken path: NaN; a one-point
+// path: the boundary value 1), and returns false when the wave has no
+// columns to stream.  m: increments of x_ia; total: columns of the run.
+// Runs longer than one pair are only formed for uniform y batches, so every
+// pair of a run has the same width.
+__device__ __forceinline__ bool wave_run(const SweepArgs& a, int64_t w, int lane, int rows,
+                                         int lam, int64_t& ia, int64_t& b0, int64_t& b1,
+                                         int32_t& m, int64_t& total) {
   if (a.mode == 0) {
     ia = w;
     b0 = w;
@@ -114,14 +111,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     b0 = (w - ia * a.runs_per_row) * a.run;
     b1 = b0 + a.run < a.ny ? b0 + a.run : a.ny;
     if (a.mode == 2 && b0 < ia) b0 = ia;
-    if (b0 >= b1) return;
+    if (b0 >= b1) return false;
   }
-  const int32_t m = n_inc(a.x_n, a.x_len, ia);
-
-  // Pairs with nothing to sweep: a broken path (NaN), the diagonal of an
-  // unbiased Gram (0), a one-point path (boundary value 1).  The stream below
-  // gives such pairs zero columns.
-  int64_t total = 0;
+  m = n_inc(a.x_n, a.x_len, ia);
+  total = 0;
   for (int64_t b = b0; b < b1; ++b) {
     const int32_t nb = n_inc(a.y_n, a.y_len, b);
     float v = 0.0f;
@@ -138,12 +131,67 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
       store_out(a, ia, b, v);
     }
   }
-  if (m <= 0 || total == 0) return;
-  const int M = m << LAM;
-  if (M > 64 * R) {  // excluded by the host; never read past the lane rows
+  if (m <= 0 || total == 0) return false;
+  if (((int64_t)m << lam) > rows) {  // excluded by the host; never read past the lane rows
     for (int64_t b = b0 + lane; b < b1; b += 64) store_out(a, ia, b, __builtin_nanf(""));
-    return;
+    return false;
   }
+  return true;
+}
+
+// One step of a lane: its R x S block of fine cells (R rows, the S = 2^LAM
+// fine columns of one coarse column), in antidiagonal order so that the S
+// columns form independent dependency chains for the scheduler.
+//   u[r]     in: the lane's values at the previous fine column; out: at the last
+//   up[cc]   the row above the strip (from lane l-1) at fine column cc
+//   up_last  the row above at the previous fine column (C of the corner cell)
+//   pub[cc]  out: the strip's bottom row, for lane l+1
+//   gk[c]    cell factor of coarse row c of the strip
+//   sp       STORE: the R*S cell sums A + B of this step (lane-contiguous)
+template <int R, int LAM, int CR, bool STORE>
+__device__ __forceinline__ void advance_block(double (&u)[R], const double (&up)[1 << LAM],
+                                              double& up_last, double (&pub)[1 << LAM],
+                                              const double (&gk)[CR], float* __restrict__ sp) {
+  constexpr int S = 1 << LAM;
+  double v[R][S];
+  float sv[STORE ? R * S : 1];
+#pragma unroll
+  for (int dgl = 0; dgl < R + S - 1; ++dgl) {
+#pragma unroll
+    for (int cc = 0; cc < S; ++cc) {
+      const int r = dgl - cc;
+      if (r < 0 || r >= R) continue;
+      const double A = (cc == 0) ? u[r] : v[r][cc - 1];
+      const double B = (r == 0) ? up[cc] : v[r - 1][cc];
+      const double C = (r == 0) ? ((cc == 0) ? up_last : up[cc - 1])
+                                : ((cc == 0) ? u[r - 1] : v[r - 1][cc - 1]);
+      const double AB = A + B;
+      if constexpr (STORE) sv[r * S + cc] = (float)AB;
+      v[r][cc] = __builtin_fma(gk[(R >= S) ? (r >> LAM) : 0], AB, -C);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) u[r] = v[r][S - 1];
+  if constexpr (STORE) store_cells<R * S>(sp, sv);
+#pragma unroll
+  for (int cc = 0; cc < S; ++cc) pub[cc] = v[R - 1][cc];
+  up_last = up[S - 1];
+}
+
+template <int R, int LAM, int D, bool STORE>
+__global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
+  constexpr int DP = (D + 3) & ~3;
+  constexpr int S = 1 << LAM;                          // fine columns per coarse column
+  constexpr int CR = (R >> LAM) > 0 ? (R >> LAM) : 1;  // coarse rows per lane
+
+  const int lane = threadIdx.x & 63;
+  const int64_t w = a.wave0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= a.wave0 + a.n_waves) return;  // uniform per wave
+
+  int64_t ia, b0, b1, total;
+  int32_t m;
+  if (!wave_run(a, w, lane, 64 * R, LAM, ia, b0, b1, m, total)) return;
+  const int M = m << LAM;
 
   // Lane strips are aligned to the bottom of the grid: cell row M - 1 is the
   // last row of lane 63, and the rows above row 0 that the top strip covers
@@ -221,31 +269,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
         const double h = (double)h32[c];
         gk[c] = a.implicit ? (2.0 + h) / (2.0 - h) : 1.0 + h;
       }
-      // the R x S block of this step in antidiagonal order: S independent
-      // dependency chains for the scheduler
-      double v[R][S];
-      float sv[STORE ? R * S : 1];
-#pragma unroll
-      for (int dgl = 0; dgl < R + S - 1; ++dgl) {
-#pragma unroll
-        for (int cc = 0; cc < S; ++cc) {
-          const int r = dgl - cc;
-          if (r < 0 || r >= R) continue;
-          const double A = (cc == 0) ? u[r] : v[r][cc - 1];
-          const double B = (r == 0) ? up[cc] : v[r - 1][cc];
-          const double C = (r == 0) ? ((cc == 0) ? up_last : up[cc - 1])
-                                    : ((cc == 0) ? u[r - 1] : v[r - 1][cc - 1]);
-          const double AB = A + B;
-          if constexpr (STORE) sv[r * S + cc] = (float)AB;
-          v[r][cc] = __builtin_fma(gk[(R >= S) ? (r >> LAM) : 0], AB, -C);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r) u[r] = v[r][S - 1];
-      if constexpr (STORE) store_cells<R * S>(sp, sv);
-#pragma unroll
-      for (int cc = 0; cc < S; ++cc) pub[cc] = v[R - 1][cc];
-      up_last = up[S - 1];
+      advance_block<R, LAM, CR, STORE>(u, up, up_last, pub, gk, sp);
       if (++q == cn) {
         // last column of a pair: emit its terminal value, then the left
         // boundary (value 1) of the next pair of the run

@@ -1,11 +1,13 @@
 // Instantiations of one sweep kernel (SK_KIND: forward, forward with store,
-// adjoint) at one dyadic order SK_LAM.  Included by sweep_k{kind}_l{lam}.hip
+// adjoint, persistent pairs, lifted forward) at one dyadic order SK_LAM.  Included by sweep_k{kind}_l{lam}.hip
 // so that the configurations compile in parallel translation units.
 #include "dispatch.h"
 #if SK_KIND == 2
 #include "sweep_bwd_kernel.h"
 #elif SK_KIND == 3
 #include "pair_kernel.h"
+#elif SK_KIND == 4
+#include "lifted_kernel.h"
 #else
 #include "sweep_fwd_kernel.h"
 #endif
@@ -49,6 +51,17 @@ struct Pair {
       return nullptr;
   }
 };
+#elif SK_KIND == 4
+struct Lifted {
+  using Fn = void*;
+  template <int R, int LAM, int D>
+  static Fn get() {
+    if constexpr (lifted_fits(R, LAM, D))
+      return reinterpret_cast<void*>(&lift::lifted_sweep_kernel<R, LAM, D>);
+    else
+      return nullptr;
+  }
+};
 #else
 struct Adjoint {
   using Fn = void*;
@@ -83,6 +96,8 @@ void* SK_CAT(SK_CAT(sweep_fn_k0_l, SK_LAM), _)(int R, int d) { return pick_fixed
 void* SK_CAT(SK_CAT(sweep_fn_k1_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<FwdStore>(R, d); }
 #elif SK_KIND == 3
 void* SK_CAT(SK_CAT(sweep_fn_k3_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Pair>(R, d); }
+#elif SK_KIND == 4
+void* SK_CAT(SK_CAT(sweep_fn_k4_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Lifted>(R, d); }
 #else
 void* SK_CAT(SK_CAT(sweep_fn_k2_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Adjoint>(R, d); }
 #endif

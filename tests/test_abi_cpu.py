@@ -40,7 +40,7 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 
 def test_status_strings():
-    for code in range(-8, 1):
+    for code in range(-9, 1):
         s = sk.status_string(code)
         assert isinstance(s, str) and s
     assert sk.status_string(123) == "unknown status"
@@ -149,3 +149,54 @@ def test_implicit_flag_only_where_defined():
                                         FAKE, None) == _lib.SK_ERR_FLAGS
     assert lib.sigkernel_mmd2(ctypes.byref(X), ctypes.byref(X), 1, _lib.SK_IMPLICIT, FAKE, FAKE,
                               FAKE, 1 << 30, None) == _lib.SK_ERR_FLAGS
+
+
+def call_lifted(fn, X, Y, kernel, lam=1, flags=0, out=FAKE, ws=FAKE, nbytes=1 << 30):
+    lib = _lib.load()
+    return getattr(lib, fn)(ctypes.byref(X), ctypes.byref(Y), lam, flags,
+                            ctypes.byref(kernel) if kernel is not None else None, out, ws,
+                            nbytes, None)
+
+
+@pytest.mark.parametrize("fn", ["sigkernel_pair_lifted", "sigkernel_gram_lifted"])
+def test_lifted_argument_errors(fn):
+    X = paths()
+    rbf = _lib.SkStaticKernel(_lib.SK_STATIC_RBF, 0, 1.0)
+    assert call_lifted(fn, X, X, None) == _lib.SK_ERR_NULL
+    for bad in (_lib.SkStaticKernel(7, 0, 1.0), _lib.SkStaticKernel(_lib.SK_STATIC_RBF, 0, 0.0),
+                _lib.SkStaticKernel(_lib.SK_STATIC_RBF, 0, -1.0),
+                _lib.SkStaticKernel(_lib.SK_STATIC_RBF, 0, float("nan")),
+                _lib.SkStaticKernel(_lib.SK_STATIC_RBF, 0, float("inf")),
+                _lib.SkStaticKernel(_lib.SK_STATIC_RBF, 0, 1e-200)):
+        assert call_lifted(fn, X, X, bad) == _lib.SK_ERR_VALUE
+    # 16-bit increments only mean something for the linear kernel
+    assert call_lifted(fn, X, X, rbf, flags=_lib.SK_GRAM_BF16) == _lib.SK_ERR_FLAGS
+    assert call_lifted(fn, X, X, rbf, flags=1 << 12) == _lib.SK_ERR_FLAGS
+    assert call_lifted(fn, X, X, rbf, lam=4) == _lib.SK_ERR_ORDER
+    assert call_lifted(fn, X, paths(d=2), rbf) == _lib.SK_ERR_SHAPE
+    assert call_lifted(fn, X, X, rbf, ws=None) == _lib.SK_ERR_WORKSPACE
+    assert call_lifted(fn, X, X, rbf, nbytes=16) == _lib.SK_ERR_WORKSPACE
+    # RBF x paths taller than one wave's rows are not compiled
+    tall = paths(n=2, L=70000, d=1)
+    assert call_lifted(fn, tall, tall, rbf, lam=0) == _lib.SK_ERR_UNSUPPORTED
+    if fn == "sigkernel_pair_lifted":
+        assert call_lifted(fn, X, X, rbf, flags=_lib.SK_SYMMETRIC) == _lib.SK_ERR_FLAGS
+        assert call_lifted(fn, X, paths(n=3), rbf) == _lib.SK_ERR_SHAPE
+    else:
+        assert call_lifted(fn, X, paths(n=4, L=16, d=3, pts=FAKE + 64), rbf,
+                           flags=_lib.SK_SYMMETRIC) == _lib.SK_ERR_SHAPE
+        assert call_lifted(fn, X, X, rbf, flags=_lib.SK_NO_DIAG) == _lib.SK_ERR_FLAGS
+
+
+def test_lifted_workspace_covers_both_static_kernels():
+    lib = _lib.load()
+    X, Y = paths(n=5, L=40, d=3), paths(n=7, L=30, d=3)
+    for op, plain in ((_lib.SK_OP_PAIR_LIFTED, _lib.SK_OP_PAIR),
+                      (_lib.SK_OP_GRAM_LIFTED, _lib.SK_OP_GRAM)):
+        b = lib.sigkernel_workspace_bytes(op, ctypes.byref(X), ctypes.byref(X if op == 7 else Y),
+                                          1, 0)
+        p = lib.sigkernel_workspace_bytes(plain, ctypes.byref(X),
+                                          ctypes.byref(X if op == 7 else Y), 1, 0)
+        # node rows of both batches (padded to 4 channels, 128 rows each side)
+        nodes = (5 * 40 + 256) * 4 * 4 + ((5 if op == 7 else 7) * (40 if op == 7 else 30) + 256) * 16
+        assert b >= max(p, nodes)
