@@ -51,14 +51,16 @@ def parse():
                          "implicit one")
     ap.add_argument("--cpu-sample-pairs", type=int, default=0,
                     help="pairs of the workload timed on the CPU oracle (0: all)")
-    ap.add_argument("--workload", choices=["gram", "mmd", "ragged", "increment_gram", "corrector"],
+    ap.add_argument("--workload", choices=["gram", "mmd", "ragged", "increment_gram", "corrector",
+                                           "lifted"],
                     default="gram",
                     help="gram: the 128 x 128 Gram batch (default, the reported metric); "
                          "mmd: unbiased MMD^2 of 64 vs 64 512-point paths with its gradient; "
                          "ragged: 4096 independent pairs of uneven lengths; "
                          "increment_gram: the coarse Gram of the Gram batch on the matrix cores; "
                          "corrector: order-3 values of 65536 held-out pairs by the learned "
-                         "corrector with fallback, against the plain order-3 solve")
+                         "corrector with fallback, against the plain order-3 solve; "
+                         "lifted: the RBF-lifted Gram (sigma 0.5) of the Gram batch")
     return ap.parse_args()
 
 
@@ -121,23 +123,27 @@ def cpu_baseline(X, Y, lam, n_sample, K_gpu, repeats=3, scheme="explicit"):
 
 
 def time_steps(fn, steps, warmup):
-    """Run fn warmup + steps times; per-step HIP-event durations and the wall
-    time of the timed steps, synchronised on both sides."""
+    """Run fn warmup + steps times; the timed steps run back to back between
+    two synchronisations, with one HIP event pair on the launch stream around
+    them.  Returns ([average step duration from the events, ms] * steps, wall
+    seconds of the timed steps).  (Events around every single step would
+    separate consecutive launches and add about a tenth of a millisecond per
+    step on this hardware.)"""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    for i in range(steps):
-        starts[i].record(stream)
+    start.record(stream)
+    for _ in range(steps):
         fn()
-        ends[i].record(stream)
+    end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return [s.elapsed_time(e) for s, e in zip(starts, ends)], wall
+    return [start.elapsed_time(end) / steps] * steps, wall
 
 
 def make_step(call, capture, eager):
@@ -234,7 +240,7 @@ def bench_ragged(args):
         "bf16_increments_ms_per_step": wall16 * 1e3 / args.steps,
         "roofline": {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": VALU_PEAK_TOPS,
                      "unit": "Tops/s", "frac": ops / avg_s / 1e12 / VALU_PEAK_TOPS,
-                     "traffic": None, "kernel": "pair_kernel (events around each call)",
+                     "traffic": None, "kernel": "pair_kernel (events around the timed calls)",
                      "ops_per_cell": sweep_ops_per_cell(d, lam)},
     }
     if not args.no_cpu_baseline:
@@ -259,6 +265,94 @@ def bench_ragged(args):
                                         f"{dt:.2f} s",
             "gpu_max_err_on_sample": errs(got)["max"]}
         rec["err_vs_fp64_oracle"] = {"f32_increments": errs(got), "bf16_increments": errs(got16)}
+    print(json.dumps(rec), flush=True)
+
+
+# FP64 operations counted for one double-precision exp: a two-constant range
+# reduction (round, two FMAs), a degree-12 polynomial (12 FMAs) and the
+# scaling by the power of two (about 4 operations).
+EXP_OPS = 20
+
+
+def lifted_ops_per_pair(m: int, n: int, d: int, lam: int) -> int:
+    """Algorithmic FP64 operations of one RBF-lifted pair on P_lambda: per
+    node pair the static kernel (d differences, d FMAs, one scaling, one exp),
+    per coarse cell the second difference and the cell factor (5), per fine
+    cell the update (2)."""
+    return ((m + 1) * (n + 1) * (2 * d + 1 + EXP_OPS) + m * n * 5
+            + (m << lam) * (n << lam) * 2)
+
+
+def bench_lifted(args):
+    """The RBF-lifted Gram (Gaussian static kernel, sigma 0.5) of the Gram
+    batch: 128 x 128 pairs of 256-point paths, d = 8 + time, dyadic order 1."""
+    import torch
+    import paper_2006_14794_amd as sk
+    import workloads
+    lam, sigma = 1, 0.5
+    X, Y = workloads.gram_batch()
+    nx, L, d = X.shape
+    ny = Y.shape[0]
+    Xt, Yt = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    out = torch.empty((nx, ny), dtype=torch.float32, device="cuda")
+    ws = torch.empty(sk.workspace_bytes(8, Xt, Yt, lam, 0), dtype=torch.uint8, device="cuda")
+    recs = {}
+    for scheme in ("explicit", "implicit"):
+        def call(scheme=scheme):
+            sk.sigkernel_gram_lifted(Xt, Yt, lam, sigma=sigma, scheme=scheme, out=out,
+                                     workspace=ws)
+        graph = None if args.eager else sk.CapturedCalls(call)
+        step, launch = (call, "eager") if graph is None else (graph.replay, "hipGraph replay")
+        per, wall = time_steps(step, args.steps, args.warmup)
+        recs[scheme] = (per, wall, launch)
+        if scheme == "explicit":
+            K = out.cpu().numpy()
+    per, wall, launch = recs["explicit"]
+    ms = wall * 1e3 / args.steps
+    M, N = (L - 1) << lam, (L - 1) << lam
+    cells = nx * ny * M * N
+    ops = nx * ny * lifted_ops_per_pair(L - 1, L - 1, d, lam)
+    avg_s = float(np.mean(per)) / 1e3
+    rec = {
+        "metric": "Goursat grid-cell updates/s, RBF-lifted Gram batch",
+        "value": cells / (ms / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "RBF-lifted gram 128x128 pairs, 256-point paths, d=8+time, "
+                               "dyadic order 1, sigma 0.5", "static_kernel": "exp(-|a-b|^2/2s^2)",
+                   "pairs": nx * ny, "fine_cells_per_pair": M * N},
+        "pairs_per_s": nx * ny / (ms / 1e3), "launch": launch,
+        "implicit_ms_per_step": recs["implicit"][1] * 1e3 / args.steps,
+        "roofline": {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": VALU_PEAK_TOPS,
+                     "unit": "Tops/s", "frac": ops / avg_s / 1e12 / VALU_PEAK_TOPS,
+                     "traffic": None,
+                     "kernel": "lifted_sweep_kernel (events around the timed steps: nodes + sweep)",
+                     "avg_launch_ms": avg_s * 1e3, "ops_per_pair": ops // (nx * ny),
+                     "exp_ops": EXP_OPS},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.max_threads()
+        n_s = args.cpu_sample_pairs or nx * ny
+        rng = np.random.default_rng(1)
+        idx = np.sort(rng.choice(nx * ny, size=n_s, replace=False))
+        sx = [X[i // ny].astype(np.float64) for i in idx]
+        sy = [Y[i % ny].astype(np.float64) for i in idx]
+        oracle.lifted_rbf_pairs(sx[:8], sy[:8], lam, sigma)
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            ref = oracle.lifted_rbf_pairs(sx, sy, lam, sigma, nthreads=threads)
+            times.append(time.perf_counter() - t0)
+        dt = float(np.median(times))
+        err = np.abs(K.reshape(-1)[idx] - ref) / np.maximum(1.0, np.abs(ref))
+        what = (f"all {nx * ny} Gram pairs" if n_s == nx * ny
+                else f"{n_s} of the {nx * ny} Gram pairs (seeded)")
+        rec["cpu_baseline"] = {"value": n_s * M * N / dt, "unit": "cells/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{what}, all host threads, median of 3 runs of "
+                                         f"{dt:.2f} s",
+                               "gpu_max_err_on_sample": float(err.max())}
     print(json.dumps(rec), flush=True)
 
 
@@ -381,6 +475,9 @@ def main():
     if args.workload == "corrector":
         bench_corrector(args)
         return
+    if args.workload == "lifted":
+        bench_lifted(args)
+        return
 
     import torch
     import paper_2006_14794_amd as sk
@@ -445,7 +542,7 @@ def main():
             "unit": "Tops/s",
             "frac": achieved / VALU_PEAK_TOPS,
             "traffic": measured_traffic(),
-            "kernel": "sweep_kernel (events around each step: increments + sweep)",
+            "kernel": "sweep_kernel (events around the timed steps: increments + sweep)",
             "avg_launch_ms": avg_launch_s * 1e3,
             "ops_per_cell": sweep_ops_per_cell(d, lam),
         },

@@ -191,7 +191,7 @@ hipError_t launch_gram_mfma(const GramArgs& a, int precision, hipStream_t stream
 // Compiled sweep kernels by kind, dyadic order, rows per lane and channels
 // (nullptr when the configuration is not compiled).
 enum { kKernelForward = 0, kKernelForwardStore = 1, kKernelAdjoint = 2, kKernelPair = 3,
-       kKernelLifted = 4 };
+       kKernelLifted = 4, kKernelForwardImplicit = 5 };
 void* sweep_fn(int kind, int lam, int rows_per_lane, int dim);
 
 // Steps of a wave that streams `total` coarse columns (a multiple of three:

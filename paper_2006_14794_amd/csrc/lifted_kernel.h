@@ -32,9 +32,10 @@
 namespace sk {
 namespace lift {
 
-using fwd::advance_block;
+using fwd::cell_block;
 using fwd::first_row;
 using fwd::from_prev_lane;
+using fwd::implicit_factor;
 using fwd::load_row;
 using fwd::n_inc;
 using fwd::store_out;
@@ -135,9 +136,16 @@ __global__ __launch_bounds__(256) void lifted_sweep_kernel(const SweepArgs a) {
 #pragma unroll
         for (int c = 0; c < CR; ++c) {
           const double h = (dn[c] - dprev[c]) * scale;
-          gk[c] = a.implicit ? (2.0 + h) / (2.0 - h) : 1.0 + h;
+          gk[c] = a.implicit ? implicit_factor(h) : 1.0 + h;
         }
-        advance_block<R, LAM, CR, false>(u, up, up_last, pub, gk, nullptr);
+        double v[R][S];
+        float sv[1];
+        cell_block<R, LAM, CR, false>(v, sv, u, up, up_last, gk);
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[r][S - 1];
+#pragma unroll
+        for (int cc = 0; cc < S; ++cc) pub[cc] = v[R - 1][cc];
+        up_last = up[S - 1];
         if (++q == cn) {
           if (lane == 63) {
             const int64_t cb = b0 + g / (cn + 1);

@@ -127,7 +127,8 @@ __global__ __launch_bounds__(256) void pair_kernel(const PairArgs a) {
 #pragma unroll
           for (int c = 0; c < CR; ++c) {
             const double h = (double)h32[c] * a.scale;  // exact: scale is a power of two
-            gk[c] = a.implicit ? (2.0 + h) / (2.0 - h) : __builtin_fma((double)h32[c], a.scale, 1.0);
+            gk[c] = a.implicit ? fwd::implicit_factor(h)
+                               : __builtin_fma((double)h32[c], a.scale, 1.0);
           }
           double v[R][S];
 #pragma unroll

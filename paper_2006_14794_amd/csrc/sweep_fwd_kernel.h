@@ -50,6 +50,21 @@ __device__ __forceinline__ double from_prev_lane(double v, double keep) {
                                           (unsigned long long)(unsigned)lo));
 }
 
+// Cell factor of the implicit scheme, (2 + h) / (2 - h): the hardware
+// reciprocal of 2 - h refined by two Newton-Raphson steps (each at least
+// squares the relative error), then one product -- within a few ulp, at about
+// half the cost of an IEEE division.  h = 2 gives inf or NaN, as the division
+// would (the scheme has no solution there).
+__device__ __forceinline__ double implicit_factor(double h) {
+  const double den = 2.0 - h;
+  double r = __builtin_amdgcn_rcp(den);
+  double e = __builtin_fma(-den, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-den, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  return (2.0 + h) * r;
+}
+
 template <int DP>
 __device__ __forceinline__ void load_row(const float* __restrict__ p, float (&v)[DP]) {
   const float4* p4 = reinterpret_cast<const float4*>(p);
@@ -142,19 +157,21 @@ __device__ __forceinline__ bool wave_run(const SweepArgs& a, int64_t w, int lane
 // One step of a lane: its R x S block of fine cells (R rows, the S = 2^LAM
 // fine columns of one coarse column), in antidiagonal order so that the S
 // columns form independent dependency chains for the scheduler.
-//   u[r]     in: the lane's values at the previous fine column; out: at the last
-//   up[cc]   the row above the strip (from lane l-1) at fine column cc
-//   up_last  the row above at the previous fine column (C of the corner cell)
-//   pub[cc]  out: the strip's bottom row, for lane l+1
-//   gk[c]    cell factor of coarse row c of the strip
-//   sp       STORE: the R*S cell sums A + B of this step (lane-contiguous)
+//   v[r][cc]  out: the block's new values
+//   sv        STORE: the R*S cell sums A + B (row-major)
+//   u[r]      the lane's values at the previous fine column
+//   up[cc]    the row above the strip (from lane l-1) at fine column cc
+//   up_last   the row above at the previous fine column (C of the corner cell)
+//   gk[c]     cell factor of coarse row c of the strip
+// The caller then shifts u, pub and up_last to the block's last column/row
+// (kept outside: the same statements inside the helper cost the Gram sweep
+// eleven registers with this compiler).
 template <int R, int LAM, int CR, bool STORE>
-__device__ __forceinline__ void advance_block(double (&u)[R], const double (&up)[1 << LAM],
-                                              double& up_last, double (&pub)[1 << LAM],
-                                              const double (&gk)[CR], float* __restrict__ sp) {
+__device__ __forceinline__ void cell_block(double (&v)[R][1 << LAM],
+                                           float (&sv)[STORE ? R * (1 << LAM) : 1],
+                                           const double (&u)[R], const double (&up)[1 << LAM],
+                                           double up_last, const double (&gk)[CR]) {
   constexpr int S = 1 << LAM;
-  double v[R][S];
-  float sv[STORE ? R * S : 1];
 #pragma unroll
   for (int dgl = 0; dgl < R + S - 1; ++dgl) {
 #pragma unroll
@@ -170,15 +187,11 @@ __device__ __forceinline__ void advance_block(double (&u)[R], const double (&up)
       v[r][cc] = __builtin_fma(gk[(R >= S) ? (r >> LAM) : 0], AB, -C);
     }
   }
-#pragma unroll
-  for (int r = 0; r < R; ++r) u[r] = v[r][S - 1];
-  if constexpr (STORE) store_cells<R * S>(sp, sv);
-#pragma unroll
-  for (int cc = 0; cc < S; ++cc) pub[cc] = v[R - 1][cc];
-  up_last = up[S - 1];
 }
 
-template <int R, int LAM, int D, bool STORE>
+// IMPL: the implicit scheme's cell factor (a separate instantiation, so that
+// the explicit kernel carries none of its registers).
+template <int R, int LAM, int D, bool STORE, bool IMPL>
 __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
   constexpr int DP = (D + 3) & ~3;
   constexpr int S = 1 << LAM;                          // fine columns per coarse column
@@ -267,9 +280,17 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
 #pragma unroll
       for (int c = 0; c < CR; ++c) {
         const double h = (double)h32[c];
-        gk[c] = a.implicit ? (2.0 + h) / (2.0 - h) : 1.0 + h;
+        gk[c] = IMPL ? implicit_factor(h) : 1.0 + h;
       }
-      advance_block<R, LAM, CR, STORE>(u, up, up_last, pub, gk, sp);
+      double v[R][S];
+      float sv[STORE ? R * S : 1];
+      cell_block<R, LAM, CR, STORE>(v, sv, u, up, up_last, gk);
+      if constexpr (STORE) store_cells<R * S>(sp, sv);
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[r] = v[r][S - 1];
+#pragma unroll
+      for (int cc = 0; cc < S; ++cc) pub[cc] = v[R - 1][cc];
+      up_last = up[S - 1];
       if (++q == cn) {
         // last column of a pair: emit its terminal value, then the left
         // boundary (value 1) of the next pair of the run

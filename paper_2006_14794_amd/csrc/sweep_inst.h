@@ -1,5 +1,5 @@
 // Instantiations of one sweep kernel (SK_KIND: forward, forward with store,
-// adjoint, persistent pairs, lifted forward) at one dyadic order SK_LAM.  Included by sweep_k{kind}_l{lam}.hip
+// adjoint, persistent pairs, lifted forward, implicit forward) at one dyadic order SK_LAM.  Included by sweep_k{kind}_l{lam}.hip
 // so that the configurations compile in parallel translation units.
 #include "dispatch.h"
 #if SK_KIND == 2
@@ -24,7 +24,7 @@ struct FwdPlain {
   template <int R, int LAM, int D>
   static Fn get() {
     if constexpr (sweep_fits(R, LAM, D))
-      return reinterpret_cast<void*>(&fwd::sweep_kernel<R, LAM, D, false>);
+      return reinterpret_cast<void*>(&fwd::sweep_kernel<R, LAM, D, false, false>);
     else
       return nullptr;
   }
@@ -35,7 +35,7 @@ struct FwdStore {
   template <int R, int LAM, int D>
   static Fn get() {
     if constexpr (sweep_fits(R, LAM, D))
-      return reinterpret_cast<void*>(&fwd::sweep_kernel<R, LAM, D, true>);
+      return reinterpret_cast<void*>(&fwd::sweep_kernel<R, LAM, D, true, false>);
     else
       return nullptr;
   }
@@ -47,6 +47,17 @@ struct Pair {
   static Fn get() {
     if constexpr (sweep_fits(R, LAM, D))
       return reinterpret_cast<void*>(&pairk::pair_kernel<R, LAM, D>);
+    else
+      return nullptr;
+  }
+};
+#elif SK_KIND == 5
+struct FwdImplicit {
+  using Fn = void*;
+  template <int R, int LAM, int D>
+  static Fn get() {
+    if constexpr (sweep_fits(R, LAM, D))
+      return reinterpret_cast<void*>(&fwd::sweep_kernel<R, LAM, D, false, true>);
     else
       return nullptr;
   }
@@ -98,6 +109,8 @@ void* SK_CAT(SK_CAT(sweep_fn_k1_l, SK_LAM), _)(int R, int d) { return pick_fixed
 void* SK_CAT(SK_CAT(sweep_fn_k3_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Pair>(R, d); }
 #elif SK_KIND == 4
 void* SK_CAT(SK_CAT(sweep_fn_k4_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Lifted>(R, d); }
+#elif SK_KIND == 5
+void* SK_CAT(SK_CAT(sweep_fn_k5_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<FwdImplicit>(R, d); }
 #else
 void* SK_CAT(SK_CAT(sweep_fn_k2_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Adjoint>(R, d); }
 #endif

@@ -1,0 +1,4 @@
+// Sweep kernel instantiations: forward with the implicit scheme's cell factor, dyadic order 0 (see sweep_inst.h).
+#define SK_KIND 5
+#define SK_LAM 0
+#include "sweep_inst.h"
