@@ -14,6 +14,13 @@
  * Rows of the fine grid follow x, columns follow y; the fine grid has
  * (2^lambda (lx-1) + 1) x (2^lambda (ly-1) + 1) nodes.
  *
+ * Dyadic order: any lambda >= 0 with 2^lambda (len - 1) <= 2^20 for every
+ * path of both batches (else SK_ERR_ORDER); the lifted calls and the
+ * corrector's fallback take lambda <= 3.  The sweeps are compiled for orders
+ * 0..3; a higher order runs at order 3 on the increments split into
+ * 2^(lambda - 3) equal parts, whose fine cells and coefficients are exactly
+ * those of P_lambda (each part is the increment times a power of two).
+ *
  * Conventions shared by every entry point
  * ---------------------------------------
  *  - All point and output buffers are DEVICE memory owned by the caller.  The
@@ -46,7 +53,7 @@ enum {
     SK_OK = 0,
     SK_ERR_NULL = -1,        /* a required pointer is NULL                         */
     SK_ERR_SHAPE = -2,       /* d < 1, a length < 1, dims or counts inconsistent   */
-    SK_ERR_ORDER = -3,       /* dyadic order < 0 or beyond what is supported        */
+    SK_ERR_ORDER = -3,       /* dyadic order < 0, or 2^lambda (len - 1) > 2^20      */
     SK_ERR_WORKSPACE = -4,   /* workspace NULL or smaller than required             */
     SK_ERR_FLAGS = -5,       /* unknown or incompatible flag bits                   */
     SK_ERR_HIP = -6,         /* a HIP launch failed                                 */

@@ -14,7 +14,43 @@ namespace {
 
 using sk::Batch;
 
-constexpr int32_t kMaxDyadicOrder = 3;
+// Dyadic orders the sweep kernels are compiled for; beyond them the batch is
+// refined (split_order) and swept at the highest compiled order.
+constexpr int32_t kMaxKernelOrder = 3;
+// Fine rows or columns of one pair: 2^lambda (len - 1) <= 2^20.
+constexpr int64_t kMaxFineSide = int64_t(1) << 20;
+
+// A dyadic order lambda > kMaxKernelOrder runs as order k = kMaxKernelOrder on
+// the increments split into rep = 2^(lambda - k) equal parts: each coarse cell
+// of P_lambda is then rep x rep cells of the refined batch, whose fine cells
+// and coefficients G0 2^-2lambda are exactly those of P_lambda (the parts are
+// the increment times an exact power of two).
+struct Order {
+  int32_t k;
+  int32_t rep;
+};
+
+Order split_order(int32_t lam) {
+  if (lam <= kMaxKernelOrder) return Order{lam, 1};
+  return Order{kMaxKernelOrder, 1 << (lam - kMaxKernelOrder)};
+}
+
+// The batch as the kernels see it after refinement (len - 1 increments become
+// rep (len - 1)); the points pointer is unchanged.
+sk_paths refined(const sk_paths* p, int32_t rep) {
+  sk_paths r = *p;
+  if (r.len > 1) r.len = (int32_t)((int64_t)(r.len - 1) * rep + 1);
+  return r;
+}
+
+// lambda >= 0 and every pair's fine grid within kMaxFineSide on each side.
+bool order_ok(int32_t lam, const sk_paths* X, const sk_paths* Y, int32_t max_order) {
+  if (lam < 0 || lam > max_order) return false;
+  for (const sk_paths* p : {X, Y})
+    if (((int64_t)(p->len > 1 ? p->len - 1 : 0) << lam) > kMaxFineSide) return false;
+  return true;
+}
+constexpr int32_t kMaxDyadicOrder = 20;
 
 bool valid_batch(const sk_paths* p) {
   if (!p) return false;
@@ -93,7 +129,12 @@ struct PairLayout {
   size_t order, counts, bands, total;
 };
 
-PairLayout pair_layout(const sk_paths* X, const sk_paths* Y, int32_t lam, bool gram) {
+PairLayout pair_layout(const sk_paths* X0, const sk_paths* Y0, int32_t lam0, bool gram) {
+  const Order o = split_order(lam0);
+  const sk_paths Xr = refined(X0, o.rep), Yr = refined(Y0, o.rep);
+  const sk_paths* X = &Xr;
+  const sk_paths* Y = &Yr;
+  const int32_t lam = o.k;
   PairLayout L{};
   const int64_t npairs = gram ? X->n_paths * Y->n_paths : X->n_paths;
   const int d = X->dim;
@@ -123,6 +164,17 @@ PairLayout pair_layout(const sk_paths* X, const sk_paths* Y, int32_t lam, bool g
   return L;
 }
 
+// Workspace of a Gram call: the one-wave sweep's layout or, for x paths too
+// tall for it, the persistent pair kernel's.
+size_t gram_ws(const sk_paths* X, const sk_paths* Y, int32_t lam) {
+  const Order o = split_order(lam);
+  const sk_paths Xr = refined(X, o.rep), Yr = refined(Y, o.rep);
+  const size_t f = forward_ws(&Xr, &Yr);
+  if (X->dim != Y->dim) return f;
+  const size_t g = pair_layout(X, Y, lam, true).total;
+  return f > g ? f : g;
+}
+
 // Backward workspace: the forward layout, then the per-wave store of one
 // chunk of waves, the per-run x-side and per-pair y-side increment gradients.
 constexpr size_t kStoreCapBytes = size_t(4) << 30;
@@ -135,7 +187,13 @@ struct BackwardPlan {
   size_t store_off, partx_off, party_off, total;
 };
 
-BackwardPlan backward_plan(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t flags) {
+BackwardPlan backward_plan(const sk_paths* X0, const sk_paths* Y0, int32_t lam0,
+                           uint32_t flags) {
+  const Order o = split_order(lam0);
+  const sk_paths Xr = refined(X0, o.rep), Yr = refined(Y0, o.rep);
+  const sk_paths* X = &Xr;
+  const sk_paths* Y = &Yr;
+  const int32_t lam = o.k;
   BackwardPlan P{};
   const int64_t m = X->len - 1, n = Y->len - 1;
   const int64_t fine_rows = m << lam;
@@ -144,7 +202,7 @@ BackwardPlan backward_plan(const sk_paths* X, const sk_paths* Y, int32_t lam, ui
     P.total = forward_ws(X, Y);
     return P;
   }
-  const sk_tune t = sk::tuning_for(SK_OP_GRAM_BACKWARD, X, Y, lam, flags);
+  const sk_tune t = sk::tuning_for(SK_OP_GRAM_BACKWARD, X0, Y0, lam0, flags);
   P.waves_per_block = t.waves_per_block;
   P.run = choose_run(X->n_paths, Y->n_paths, t.run);
   P.runs_per_row = (Y->n_paths + P.run - 1) / P.run;
@@ -183,17 +241,20 @@ sk_status check_flags(uint32_t flags, uint32_t allowed) {
 }
 
 // gram: every (a, b) of the two batches, out[a * ny + b]; else pairs (x_k, y_k)
-sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* out, void* ws,
+sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam0, float* out, void* ws,
                     size_t ws_bytes, hipStream_t stream, bool gram, int rounding,
                     const sk_tune& tune, bool implicit) {
   const int d = X->dim;
   const int dp = sk::padded_dim(d);
-  const PairLayout PL = pair_layout(X, Y, lam, gram);
+  const PairLayout PL = pair_layout(X, Y, lam0, gram);
   const int64_t npairs = gram ? X->n_paths * Y->n_paths : X->n_paths;
   if (npairs > INT32_MAX) return SK_ERR_UNSUPPORTED;
   if (PL.rows_hi == 0) return SK_ERR_UNSUPPORTED;
   if (ws_bytes < PL.total) return SK_ERR_WORKSPACE;
-  const ForwardLayout L = forward_layout(X, Y);
+  const Order o = split_order(lam0);
+  const int32_t lam = o.k;
+  const sk_paths Xr = refined(X, o.rep), Yr = refined(Y, o.rep);
+  const ForwardLayout L = forward_layout(&Xr, &Yr);
   char* base = static_cast<char*>(ws);
   float* incx = reinterpret_cast<float*>(base + L.incx) + sk::kStreamPad * dp;
   float* incy = reinterpret_cast<float*>(base + L.incy) + sk::kStreamPad * dp;
@@ -204,19 +265,23 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* ou
   const sk::Batch bx = to_batch(X), by = to_batch(Y);
   if (X->offsets && sk::launch_plan(bx, px, stream) != hipSuccess) return SK_ERR_HIP;
   if (Y->offsets && sk::launch_plan(by, py, stream) != hipSuccess) return SK_ERR_HIP;
-  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, 1.0f, dp, incx, stream, rounding) !=
-      hipSuccess)
+  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, 1.0f, dp, incx, stream, rounding,
+                            o.rep) != hipSuccess)
     return SK_ERR_HIP;
-  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream, rounding) !=
-      hipSuccess)
+  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream, rounding,
+                            o.rep) != hipSuccess)
+    return SK_ERR_HIP;
+  if (X->offsets && sk::launch_scale_plan(px, X->n_paths, o.rep, stream) != hipSuccess)
+    return SK_ERR_HIP;
+  if (Y->offsets && sk::launch_scale_plan(py, Y->n_paths, o.rep, stream) != hipSuccess)
     return SK_ERR_HIP;
   int32_t* order = reinterpret_cast<int32_t*>(base + PL.order);
   int32_t* counts = reinterpret_cast<int32_t*>(base + PL.counts);
   sk::PairPlanArgs pp{};
   pp.x_n = X->offsets ? px.n : nullptr;
-  pp.x_len = X->len;
+  pp.x_len = Xr.len;
   pp.y_n = Y->offsets ? py.n : nullptr;
-  pp.y_len = Y->len;
+  pp.y_len = Yr.len;
   pp.npairs = (int32_t)npairs;
   pp.gram_ny = gram ? Y->n_paths : 0;
   pp.lam = lam;
@@ -234,8 +299,8 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* ou
   a.x_start = X->offsets ? px.start : nullptr;
   a.y_n = pp.y_n;
   a.y_start = Y->offsets ? py.start : nullptr;
-  a.x_len = X->len;
-  a.y_len = Y->len;
+  a.x_len = Xr.len;
+  a.y_len = Yr.len;
   a.scale = ldexp(1.0, -(2 * lam + 1));
   a.implicit = implicit ? 1 : 0;
   a.bandbuf = reinterpret_cast<double*>(base + PL.bands);
@@ -261,29 +326,32 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam, float* ou
   return e == hipSuccess ? SK_OK : SK_ERR_HIP;
 }
 
-sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t flags,
+sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam0, uint32_t flags,
                       float* out, void* ws, size_t ws_bytes, hipStream_t stream, int mode) {
   const int rounding = rounding_of(flags);
-  const sk_tune tune = sk::tuning_for(mode == 0 ? SK_OP_PAIR : SK_OP_GRAM, X, Y, lam, flags);
+  const sk_tune tune = sk::tuning_for(mode == 0 ? SK_OP_PAIR : SK_OP_GRAM, X, Y, lam0, flags);
   const bool implicit = (flags & SK_IMPLICIT) != 0;
   if (mode == 0)
-    return run_pairs(X, Y, lam, out, ws, ws_bytes, stream, false, rounding, tune, implicit);
+    return run_pairs(X, Y, lam0, out, ws, ws_bytes, stream, false, rounding, tune, implicit);
+  const Order o = split_order(lam0);
+  const int32_t lam = o.k;
+  const sk_paths Xr = refined(X, o.rep), Yr = refined(Y, o.rep);
   const int d = X->dim;
   const int dp = sk::padded_dim(d);
-  const int64_t fine_rows = (int64_t)(X->len - 1) << lam;
+  const int64_t fine_rows = (int64_t)(Xr.len - 1) << lam;
   const int R = sk::choose_rows_per_lane(fine_rows < 1 ? 1 : fine_rows, lam, d);
   if (R == 0) {
     // x paths taller than one wave's strips: every (a, b) through the
     // persistent pair kernel with row bands (a symmetric Gram is filled in
     // both halves by solving both)
     const sk_status st =
-        run_pairs(X, Y, lam, out, ws, ws_bytes, stream, true, rounding, tune, implicit);
+        run_pairs(X, Y, lam0, out, ws, ws_bytes, stream, true, rounding, tune, implicit);
     if (st == SK_OK && mode == 2 && (flags & SK_NO_DIAG) &&
         sk::launch_zero_diag(out, X->n_paths, stream) != hipSuccess)
       return SK_ERR_HIP;
     return st;
   }
-  const ForwardLayout L = forward_layout(X, Y);
+  const ForwardLayout L = forward_layout(&Xr, &Yr);
   if (ws_bytes < L.total) return SK_ERR_WORKSPACE;
 
   char* base = static_cast<char*>(ws);
@@ -298,11 +366,15 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_
   if (Y->offsets && sk::launch_plan(by, py, stream) != hipSuccess) return SK_ERR_HIP;
   // h = G0 / 2^(2 lam + 1): fold the exact power-of-two scale into the x side
   const float scale = ldexpf(1.0f, -(2 * lam + 1));
-  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, scale, dp, incx, stream, rounding) !=
-      hipSuccess)
+  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, scale, dp, incx, stream, rounding,
+                            o.rep) != hipSuccess)
     return SK_ERR_HIP;
-  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream, rounding) !=
-      hipSuccess)
+  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream, rounding,
+                            o.rep) != hipSuccess)
+    return SK_ERR_HIP;
+  if (X->offsets && sk::launch_scale_plan(px, X->n_paths, o.rep, stream) != hipSuccess)
+    return SK_ERR_HIP;
+  if (Y->offsets && sk::launch_scale_plan(py, Y->n_paths, o.rep, stream) != hipSuccess)
     return SK_ERR_HIP;
 
   sk::SweepArgs a{};
@@ -312,8 +384,8 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_
   a.x_start = X->offsets ? px.start : nullptr;
   a.y_n = Y->offsets ? py.n : nullptr;
   a.y_start = Y->offsets ? py.start : nullptr;
-  a.x_len = X->len;
-  a.y_len = Y->len;
+  a.x_len = Xr.len;
+  a.y_len = Yr.len;
   a.nx = X->n_paths;
   a.ny = Y->n_paths;
   a.mode = mode;
@@ -358,8 +430,8 @@ Mmd2Layout mmd2_layout(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32
   off += align256(n * m * sizeof(float));
   L.tmp = off;
   off += align256((size_t)X->n_paths * X->len * X->dim * sizeof(float));
-  size_t sub = forward_ws(X, X);
-  const size_t c[] = {forward_ws(Y, Y), forward_ws(X, Y)};
+  size_t sub = gram_ws(X, X, lam);
+  const size_t c[] = {gram_ws(Y, Y, lam), gram_ws(X, Y, lam)};
   for (size_t v : c) sub = v > sub ? v : sub;
   if (flags & SK_MMD2_GRAD) {
     const size_t b1 = backward_plan(X, X, lam, SK_SYMMETRIC | SK_NO_DIAG).total;
@@ -602,12 +674,8 @@ size_t sigkernel_workspace_bytes(int32_t op, const sk_paths* X, const sk_paths* 
     case SK_OP_PAIR:
       if (X->dim != Y->dim) return 0;
       return pair_layout(X, Y, dyadic_order, false).total;
-    case SK_OP_GRAM: {
-      const size_t f = forward_ws(X, Y);
-      if (X->dim != Y->dim) return f;
-      const size_t g = pair_layout(X, Y, dyadic_order, true).total;
-      return f > g ? f : g;
-    }
+    case SK_OP_GRAM:
+      return gram_ws(X, Y, dyadic_order);
     case SK_OP_GRAM_BACKWARD:
       if (X->offsets || Y->offsets || X->dim != Y->dim) return 0;
       return backward_plan(X, Y, dyadic_order, flags).total;
@@ -642,7 +710,7 @@ sk_status sigkernel_pair(const sk_paths* x, const sk_paths* y, int32_t dyadic_or
   if (!out && x->n_paths > 0) return SK_ERR_NULL;
   if ((x->n_paths > 0 && !x->points) || (y->n_paths > 0 && !y->points)) return SK_ERR_NULL;
   if (x->dim != y->dim || x->n_paths != y->n_paths) return SK_ERR_SHAPE;
-  if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (!order_ok(dyadic_order, x, y, kMaxDyadicOrder)) return SK_ERR_ORDER;
   if (sk_status f = check_flags(flags, SK_GRAM_BF16 | SK_GRAM_F16 | SK_IMPLICIT)) return f;
   if (x->n_paths == 0) return SK_OK;
   if (!ws) return SK_ERR_WORKSPACE;
@@ -657,7 +725,7 @@ sk_status sigkernel_gram(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
   if (!K && X->n_paths > 0 && Y->n_paths > 0) return SK_ERR_NULL;
   if ((X->n_paths > 0 && !X->points) || (Y->n_paths > 0 && !Y->points)) return SK_ERR_NULL;
   if (X->dim != Y->dim) return SK_ERR_SHAPE;
-  if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (!order_ok(dyadic_order, X, Y, kMaxDyadicOrder)) return SK_ERR_ORDER;
   if (sk_status f = check_flags(
           flags, SK_SYMMETRIC | SK_NO_DIAG | SK_GRAM_BF16 | SK_GRAM_F16 | SK_IMPLICIT))
     return f;
@@ -679,7 +747,7 @@ sk_status sigkernel_pair_lifted(const sk_paths* x, const sk_paths* y, int32_t dy
   if (!out && x->n_paths > 0) return SK_ERR_NULL;
   if ((x->n_paths > 0 && !x->points) || (y->n_paths > 0 && !y->points)) return SK_ERR_NULL;
   if (x->dim != y->dim || x->n_paths != y->n_paths) return SK_ERR_SHAPE;
-  if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (!order_ok(dyadic_order, x, y, kMaxKernelOrder)) return SK_ERR_ORDER;
   if (sk_status k = check_static_kernel(kernel)) return k;
   const uint32_t allowed = kernel->kind == SK_STATIC_LINEAR ? SK_IMPLICIT | SK_GRAM_BF16 |
                                                                   SK_GRAM_F16
@@ -699,7 +767,7 @@ sk_status sigkernel_gram_lifted(const sk_paths* X, const sk_paths* Y, int32_t dy
   if (!K && X->n_paths > 0 && Y->n_paths > 0) return SK_ERR_NULL;
   if ((X->n_paths > 0 && !X->points) || (Y->n_paths > 0 && !Y->points)) return SK_ERR_NULL;
   if (X->dim != Y->dim) return SK_ERR_SHAPE;
-  if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (!order_ok(dyadic_order, X, Y, kMaxKernelOrder)) return SK_ERR_ORDER;
   if (sk_status k = check_static_kernel(kernel)) return k;
   const uint32_t allowed =
       SK_SYMMETRIC | SK_NO_DIAG | SK_IMPLICIT |
@@ -749,7 +817,7 @@ sk_status sigkernel_mmd2(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
   if (!X || !Y || !mmd2) return SK_ERR_NULL;
   if (!valid_batch(X) || !valid_batch(Y)) return SK_ERR_SHAPE;
   if (X->dim != Y->dim || X->n_paths < 2 || Y->n_paths < 2) return SK_ERR_SHAPE;
-  if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (!order_ok(dyadic_order, X, Y, kMaxDyadicOrder)) return SK_ERR_ORDER;
   if (sk_status f = check_flags(flags, SK_MMD2_GRAD)) return f;
   if ((flags & SK_MMD2_GRAD) && !dX) return SK_ERR_NULL;
   if (X->offsets || Y->offsets) return SK_ERR_UNSUPPORTED;
@@ -800,7 +868,7 @@ sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t 
   if (!X || !Y) return SK_ERR_NULL;
   if (!valid_batch(X) || !valid_batch(Y)) return SK_ERR_SHAPE;
   if (X->dim != Y->dim) return SK_ERR_SHAPE;
-  if (dyadic_order < 0 || dyadic_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (!order_ok(dyadic_order, X, Y, kMaxDyadicOrder)) return SK_ERR_ORDER;
   if (sk_status f = check_flags(flags, SK_SYMMETRIC | SK_NO_DIAG)) return f;
   const bool sym = (flags & SK_SYMMETRIC) != 0;
   if (sym && (X->points != Y->points || X->offsets != Y->offsets || X->n_paths != Y->n_paths ||
@@ -812,7 +880,9 @@ sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t 
   if (!dK || (!dX && !dY)) return SK_ERR_NULL;
   if ((X->n_paths > 0 && !X->points) || (Y->n_paths > 0 && !Y->points)) return SK_ERR_NULL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int lam = dyadic_order;
+  const Order o = split_order(dyadic_order);
+  const int lam = o.k;
+  const sk_paths Xr = refined(X, o.rep), Yr = refined(Y, o.rep);
   const int d = X->dim;
   // one-point paths: the kernel is the constant 1, every gradient is 0
   if (X->len < 2 || Y->len < 2) {
@@ -822,13 +892,13 @@ sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t 
       return SK_ERR_HIP;
     return SK_OK;
   }
-  const BackwardPlan P = backward_plan(X, Y, lam, flags);
+  const BackwardPlan P = backward_plan(X, Y, dyadic_order, flags);
   if (P.R == 0 || !sk::adjoint_supported(P.R, lam, d)) return SK_ERR_UNSUPPORTED;
   if (!ws) return SK_ERR_WORKSPACE;
   if (ws_bytes < P.total) return SK_ERR_WORKSPACE;
 
   const int dp = sk::padded_dim(d);
-  const ForwardLayout L = forward_layout(X, Y);
+  const ForwardLayout L = forward_layout(&Xr, &Yr);
   char* base = static_cast<char*>(ws);
   float* incx = reinterpret_cast<float*>(base + L.incx) + sk::kStreamPad * dp;
   float* incy = reinterpret_cast<float*>(base + L.incy) + sk::kStreamPad * dp;
@@ -837,14 +907,18 @@ sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t 
   float* part_y = reinterpret_cast<float*>(base + P.party_off);
   const sk::Batch bx = to_batch(X), by = to_batch(Y);
   const float scale = ldexpf(1.0f, -(2 * lam + 1));
-  if (sk::launch_increments(bx, nullptr, scale, dp, incx, st) != hipSuccess) return SK_ERR_HIP;
-  if (sk::launch_increments(by, nullptr, 1.0f, dp, incy, st) != hipSuccess) return SK_ERR_HIP;
+  if (sk::launch_increments(bx, nullptr, scale, dp, incx, st, sk::kRoundNone, o.rep) !=
+      hipSuccess)
+    return SK_ERR_HIP;
+  if (sk::launch_increments(by, nullptr, 1.0f, dp, incy, st, sk::kRoundNone, o.rep) !=
+      hipSuccess)
+    return SK_ERR_HIP;
 
   sk::SweepArgs fa{};
   fa.incx = incx;
   fa.incy = incy;
-  fa.x_len = X->len;
-  fa.y_len = Y->len;
+  fa.x_len = Xr.len;
+  fa.y_len = Yr.len;
   fa.nx = X->n_paths;
   fa.ny = Y->n_paths;
   fa.mode = sym ? 2 : 1;
@@ -859,8 +933,8 @@ sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t 
   sk::BwdArgs ba{};
   ba.incx = incx;
   ba.incy = incy;
-  ba.x_len = X->len;
-  ba.y_len = Y->len;
+  ba.x_len = Xr.len;
+  ba.y_len = Yr.len;
   ba.nx = X->n_paths;
   ba.ny = Y->n_paths;
   ba.mode = sym ? 2 : 1;
@@ -883,14 +957,18 @@ sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t 
     if (sk::launch_adjoint(ba, lam, P.R, d, st, P.waves_per_block) != hipSuccess)
       return SK_ERR_HIP;
   }
+  // the parts of a refined increment are the increment over rep: their
+  // gradients sum, times 1 / rep, to the increment's
+  const float inv_rep = 1.0f / (float)o.rep;
   if (dX) {
-    if (sk::launch_point_grad(part_x, P.runs_per_row, scale, sym ? part_y : nullptr, X->n_paths,
-                              Y->n_paths, sym, X->n_paths, X->len, d, dX, st) != hipSuccess)
+    if (sk::launch_point_grad(part_x, P.runs_per_row, scale * inv_rep, sym ? part_y : nullptr,
+                              X->n_paths, Y->n_paths, sym, inv_rep, o.rep, X->n_paths, X->len, d,
+                              dX, st) != hipSuccess)
       return SK_ERR_HIP;
   }
   if (dY) {
-    if (sk::launch_point_grad(nullptr, 0, 1.0f, part_y, X->n_paths, Y->n_paths, false,
-                              Y->n_paths, Y->len, d, dY, st) != hipSuccess)
+    if (sk::launch_point_grad(nullptr, 0, 1.0f, part_y, X->n_paths, Y->n_paths, false, inv_rep,
+                              o.rep, Y->n_paths, Y->len, d, dY, st) != hipSuccess)
       return SK_ERR_HIP;
   }
   return SK_OK;
@@ -1019,7 +1097,7 @@ sk_status sigkernel_corrector_predict(const sk_paths* X, const sk_paths* Y, int3
                                       float* err, int32_t* fallback, void* ws, size_t ws_bytes,
                                       void* stream) {
   if (sk_status c = check_corrector_batches(X, Y)) return c;
-  if (fallback_order < 0 || fallback_order > kMaxDyadicOrder) return SK_ERR_ORDER;
+  if (fallback_order < 0 || fallback_order > kMaxKernelOrder) return SK_ERR_ORDER;
   if (!(kappa >= 0.0f) || !(tol >= 0.0f)) return SK_ERR_FLAGS;
   const int64_t n = X->n_paths;
   if (n == 0) return SK_OK;

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(const int64_t* __restrict__ 
 __global__ __launch_bounds__(256) void increments_kernel(
     const float* __restrict__ pts, const int64_t* __restrict__ off,
     const int32_t* __restrict__ plan_n, const int64_t* __restrict__ plan_start, int32_t len,
-    int64_t n_paths, int32_t d, int32_t dpad, float scale, int32_t rounding,
+    int64_t n_paths, int32_t d, int32_t dpad, float scale, int32_t rounding, int32_t rep,
     float* __restrict__ incr) {
   const int64_t k = blockIdx.x;
   if (k >= n_paths) return;
@@ -64,16 +64,19 @@ __global__ __launch_bounds__(256) void increments_kernel(
     n = plan_n[k];
     if (n <= 0) return;
     pstart = off[k];
-    dstart = plan_start[k];
+    dstart = plan_start[k] * rep;
   } else {
     n = len - 1;
     pstart = k * (int64_t)len;
-    dstart = k * (int64_t)n;
+    dstart = k * (int64_t)n * rep;
   }
-  const int64_t total = (int64_t)n * dpad;
+  // increment p fills rows p rep .. p rep + rep - 1 (refinement beyond the
+  // sweep's compiled orders: rep equal sub-increments of a straight segment)
+  const int64_t total = (int64_t)n * rep * dpad;
   for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
-    const int64_t p = e / dpad;
-    const int c = (int)(e - p * dpad);
+    const int64_t row = e / dpad;
+    const int64_t p = row / rep;
+    const int c = (int)(e - row * dpad);
     float v = 0.0f;
     if (c < d) {
       const float a = pts[(pstart + p + 1) * d + c];
@@ -83,10 +86,21 @@ __global__ __launch_bounds__(256) void increments_kernel(
       // products and their sums stay float32
       if (rounding == kRoundBf16) v = __bfloat162float(__float2bfloat16(v));
       if (rounding == kRoundF16) v = __half2float(__float2half(v));
-      v *= scale;  // power-of-two scale: exact
+      v *= scale;  // power-of-two scale (including 1 / rep): exact
     }
-    incr[(dstart + p) * dpad + c] = v;
+    incr[(dstart + row) * dpad + c] = v;
   }
+}
+
+// Plans of a batch refined rep times: n -> n rep (broken paths keep n < 0),
+// start -> start rep.
+__global__ __launch_bounds__(256) void scale_plan_kernel(int32_t* __restrict__ n,
+                                                         int64_t* __restrict__ start,
+                                                         int64_t n_paths, int32_t rep) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_paths) return;
+  if (n[k] > 0) n[k] *= rep;
+  start[k] *= rep;
 }
 
 // One workgroup per path: its points as dense padded rows [start + k, start
@@ -141,12 +155,20 @@ hipError_t launch_plan(const Batch& b, PathPlan plan, hipStream_t stream) {
 }
 
 hipError_t launch_increments(const Batch& b, const PathPlan* plan, float scale, int dpad,
-                             float* incr, hipStream_t stream, int rounding) {
+                             float* incr, hipStream_t stream, int rounding, int rep) {
   if (b.n_paths == 0 || (!b.offsets && b.len < 2)) return hipSuccess;
   hipLaunchKernelGGL(increments_kernel, dim3((unsigned)b.n_paths), dim3(256), 0, stream,
                      b.points, b.offsets, plan ? plan->n : nullptr,
-                     plan ? plan->start : nullptr, b.len, b.n_paths, b.dim, dpad, scale,
-                     rounding, incr);
+                     plan ? plan->start : nullptr, b.len, b.n_paths, b.dim, dpad,
+                     scale / (float)rep, rounding, rep, incr);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_plan(PathPlan plan, int64_t n_paths, int rep, hipStream_t stream) {
+  if (n_paths == 0 || rep == 1) return hipSuccess;
+  const int64_t blocks = (n_paths + 255) / 256;
+  hipLaunchKernelGGL(scale_plan_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, plan.n,
+                     plan.start, n_paths, rep);
   return hipGetLastError();
 }
 

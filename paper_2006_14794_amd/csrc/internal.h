@@ -40,9 +40,16 @@ hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t stream);
 // p < n[k], zero-padded to `dpad` channels.  scale is a power of two.  With
 // rounding kRoundBf16 / kRoundF16 each increment is first rounded to that
 // 16-bit format (the inner products then see 16-bit inputs, float32 sums).
+// With rep > 1 (a power of two) every increment fills rep consecutive rows,
+// each scale * (x_{p+1} - x_p) / rep: the batch refined rep times, exactly
+// (rows start[k] rep + p rep + j).
 enum { kRoundNone = 0, kRoundBf16 = 1, kRoundF16 = 2 };
 hipError_t launch_increments(const Batch& b, const PathPlan* plan, float scale, int dpad,
-                             float* incr, hipStream_t stream, int rounding = kRoundNone);
+                             float* incr, hipStream_t stream, int rounding = kRoundNone,
+                             int rep = 1);
+// The plan of a batch refined rep times: n[k] -> n[k] rep (for n[k] > 0),
+// start[k] -> start[k] rep.  Run after launch_increments has read the plan.
+hipError_t launch_scale_plan(PathPlan plan, int64_t n_paths, int rep, hipStream_t stream);
 
 // Dense padded node rows (the points themselves): path k occupies rows
 // [start[k] + k, start[k] + k + n[k] + 1) of a ragged batch, [k len, (k + 1)
@@ -51,39 +58,11 @@ hipError_t launch_increments(const Batch& b, const PathPlan* plan, float scale, 
 hipError_t launch_nodes(const Batch& b, const PathPlan* plan, int dpad, float* nodes,
                         hipStream_t stream);
 
-// Work description of one forward sweep launch.
-struct SweepArgs {
-  const float* incx;        // dense increments of the x side, pre-scaled by 2^-(2 lam + 1)
-                            // (lifted sweep: dense node rows of x, not scaled)
-  const float* incy;        // dense increments of the y side (lifted sweep: node rows of y)
-  const int32_t* x_n;       // ragged plans (nullptr for a uniform batch)
-  const int64_t* x_start;
-  const int32_t* y_n;
-  const int64_t* y_start;
-  int32_t x_len, y_len;     // points per path of a uniform batch
-  int64_t nx, ny;           // paths per batch
-  int32_t mode;             // 0: pairs (x_k, y_k); 1: Gram; 2: Gram upper triangle, mirrored
-  int32_t no_diag;          // mode 2: diagonal written as 0
-  int32_t implicit;         // 1: the implicit scheme's cell factor (2 + h) / (2 - h)
-  double lift_inv;          // lifted sweep: 1 / (2 sigma^2) of the Gaussian static kernel
-  double lift_scale;        // lifted sweep: 2^-(2 lam + 1), the coefficient's fine-cell factor
-  int32_t run;              // pairs streamed through one wave (Gram with uniform y)
-  int64_t runs_per_row;     // ceil(ny / run)
-  int64_t n_waves;
-  float* out;               // nullptr: terminal values not written
-  int64_t out_ld;           // ny for the Gram
-  // waves [wave0, wave0 + n_waves) of the run enumeration are launched
-  int64_t wave0;
-  // adjoint support: per wave, nsteps x 64 lanes x (R 2^lam) floats
-  float* store;
-  int64_t store_stride;
-};
+}  // namespace sk
 
-// Rows before and after the data of every dense increment buffer: a wave
-// streams rows g - lane for lanes 0..63 and prefetches two rows ahead, so it
-// reads rows -63 .. total + 66 of a run (steps are rounded up to a multiple
-// of three).
-constexpr int64_t kStreamPad = 128;
+#include "sweep_args.h"
+
+namespace sk {
 
 // Largest number of fine rows per lane of the one-wave sweep.
 constexpr int kMaxRowsPerLane = 32;
@@ -126,10 +105,14 @@ struct BwdArgs {
 hipError_t launch_adjoint(const BwdArgs& a, int lam, int rows_per_lane, int dim,
                           hipStream_t stream, int waves_per_block = 0);
 bool adjoint_supported(int rows_per_lane, int lam, int dim);
+// Point gradients of a Gram batch from the partial increment gradients:
+// increment p of path k collects rows p rep .. p rep + rep - 1 of its x-side
+// partials (summed over runs, times scale) and y-side partials (summed over
+// the other batch, times yscale); then dx_i = dinc_{i-1} - dinc_i.
 hipError_t launch_point_grad(const float* part_x, int64_t runs_per_row, float scale,
                              const float* part_y, int64_t part_y_rows, int64_t part_y_ld,
-                             bool col_upper, int64_t n_paths, int32_t len, int32_t d, float* out,
-                             hipStream_t stream);
+                             bool col_upper, float yscale, int32_t rep, int64_t n_paths,
+                             int32_t len, int32_t d, float* out, hipStream_t stream);
 
 hipError_t launch_mmd2_reduce(const float* kxx, int64_t n, const float* kyy, int64_t m,
                               const float* kxy, float* out, hipStream_t stream);
@@ -193,11 +176,5 @@ hipError_t launch_gram_mfma(const GramArgs& a, int precision, hipStream_t stream
 enum { kKernelForward = 0, kKernelForwardStore = 1, kKernelAdjoint = 2, kKernelPair = 3,
        kKernelLifted = 4, kKernelForwardImplicit = 5 };
 void* sweep_fn(int kind, int lam, int rows_per_lane, int dim);
-
-// Steps of a wave that streams `total` coarse columns (a multiple of three:
-// the y-row prefetch rotates three buffers).
-__host__ __device__ inline int64_t sweep_steps(int64_t total) {
-  return ((total + 63 + 2) / 3) * 3;
-}
 
 }  // namespace sk

@@ -14,6 +14,7 @@
 #pragma once
 #include <math.h>
 
+#include "internal.h"
 #include "sweep_fwd_kernel.h"
 
 namespace sk {

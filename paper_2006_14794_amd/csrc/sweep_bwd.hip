@@ -13,7 +13,8 @@ namespace {
 __global__ __launch_bounds__(256) void point_grad_kernel(
     const float* __restrict__ part_x, int64_t runs_per_row, float scale,
     const float* __restrict__ part_y, int64_t part_y_rows, int64_t part_y_ld, int32_t col_upper,
-    int64_t n_paths, int32_t len, int32_t d, float* __restrict__ out) {
+    float yscale, int32_t rep, int64_t n_paths, int32_t len, int32_t d,
+    float* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = n_paths * len * d;
   if (e >= total) return;
@@ -21,19 +22,21 @@ __global__ __launch_bounds__(256) void point_grad_kernel(
   const int64_t i = (e / d) % len;
   const int64_t k = e / ((int64_t)d * len);
   const int32_t ninc = len - 1;
+  const int64_t nrows = (int64_t)ninc * rep;  // rows per path of the partial gradients
   auto inc = [&](int64_t p) -> float {
     if (p < 0 || p >= ninc) return 0.0f;
-    float acc = 0.0f;
-    if (part_x)
-      for (int64_t j = 0; j < runs_per_row; ++j)
-        acc += part_x[((k * runs_per_row + j) * ninc + p) * d + c];
-    acc *= scale;
-    if (part_y) {
-      const int64_t aend = col_upper ? k + 1 : part_y_rows;
-      for (int64_t a2 = 0; a2 < aend; ++a2)
-        acc += part_y[((a2 * part_y_ld + k) * ninc + p) * d + c];
+    float accx = 0.0f, accy = 0.0f;
+    for (int64_t r = p * rep; r < (p + 1) * rep; ++r) {
+      if (part_x)
+        for (int64_t j = 0; j < runs_per_row; ++j)
+          accx += part_x[((k * runs_per_row + j) * nrows + r) * d + c];
+      if (part_y) {
+        const int64_t aend = col_upper ? k + 1 : part_y_rows;
+        for (int64_t a2 = 0; a2 < aend; ++a2)
+          accy += part_y[((a2 * part_y_ld + k) * nrows + r) * d + c];
+      }
     }
-    return acc;
+    return accx * scale + accy * yscale;
   };
   out[e] = inc(i - 1) - inc(i);
 }
@@ -57,14 +60,14 @@ bool adjoint_supported(int R, int lam, int d) {
 
 hipError_t launch_point_grad(const float* part_x, int64_t runs_per_row, float scale,
                              const float* part_y, int64_t part_y_rows, int64_t part_y_ld,
-                             bool col_upper, int64_t n_paths, int32_t len, int32_t d, float* out,
-                             hipStream_t stream) {
+                             bool col_upper, float yscale, int32_t rep, int64_t n_paths,
+                             int32_t len, int32_t d, float* out, hipStream_t stream) {
   const int64_t total = n_paths * len * d;
   if (total == 0) return hipSuccess;
   const int64_t blocks = (total + 255) / 256;
   hipLaunchKernelGGL(point_grad_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, part_x,
                      runs_per_row, scale, part_y, part_y_rows, part_y_ld, col_upper ? 1 : 0,
-                     n_paths, len, d, out);
+                     yscale, rep, n_paths, len, d, out);
   return hipGetLastError();
 }
 

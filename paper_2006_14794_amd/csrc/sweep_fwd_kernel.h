@@ -32,7 +32,7 @@
 #pragma once
 #include <math.h>
 
-#include "internal.h"
+#include "sweep_args.h"
 
 namespace sk {
 namespace fwd {

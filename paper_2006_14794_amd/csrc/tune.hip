@@ -43,9 +43,11 @@ sk_status run_call(int32_t op, const sk_paths* X, const sk_paths* Y, int32_t lam
 // Candidate tunings of a forward call: the knobs its launch path reads.
 std::vector<sk_tune> candidates(int32_t op, const sk_paths* X, const sk_paths* Y, int32_t lam) {
   std::vector<sk_tune> c;
+  // orders beyond the compiled ones run at order 3 on a refined batch with
+  // the same fine rows
   const int64_t fine_rows = (int64_t)(X->len > 1 ? X->len - 1 : 1) << lam;
-  const bool pair_path =
-      op == SK_OP_PAIR || sk::choose_rows_per_lane(fine_rows, lam, X->dim) == 0;
+  const bool pair_path = op == SK_OP_PAIR ||
+                         sk::choose_rows_per_lane(fine_rows, lam > 3 ? 3 : lam, X->dim) == 0;
   if (pair_path) {
     for (int b : {0, 1, 2, 3, 4, 6, 8}) c.push_back(sk_tune{0, 0, b, 0});
     return c;

@@ -81,7 +81,11 @@ def test_shape_errors():
 
 def test_order_and_flag_errors():
     assert call_gram(paths(), paths(), lam=-1) == _lib.SK_ERR_ORDER
-    assert call_gram(paths(), paths(), lam=4) == _lib.SK_ERR_ORDER
+    # 2^lambda (len - 1) <= 2^20 on both sides: 15 * 2^16 fits, 15 * 2^17 does not
+    assert call_gram(paths(L=16), paths(L=16), lam=17) == _lib.SK_ERR_ORDER
+    assert call_gram(paths(L=16), paths(L=1025), lam=11) == _lib.SK_ERR_ORDER
+    assert call_gram(paths(L=2), paths(L=2), lam=21) == _lib.SK_ERR_ORDER
+    assert call_pair(paths(L=16), paths(L=16), lam=17) == _lib.SK_ERR_ORDER
     assert call_gram(paths(), paths(), flags=1 << 20) == _lib.SK_ERR_FLAGS
     assert call_gram(paths(), paths(), flags=_lib.SK_NO_DIAG) == _lib.SK_ERR_FLAGS
     # symmetric needs X and Y to be the same batch
@@ -172,6 +176,7 @@ def test_lifted_argument_errors(fn):
     # 16-bit increments only mean something for the linear kernel
     assert call_lifted(fn, X, X, rbf, flags=_lib.SK_GRAM_BF16) == _lib.SK_ERR_FLAGS
     assert call_lifted(fn, X, X, rbf, flags=1 << 12) == _lib.SK_ERR_FLAGS
+    # the lifted sweep runs the compiled orders only
     assert call_lifted(fn, X, X, rbf, lam=4) == _lib.SK_ERR_ORDER
     assert call_lifted(fn, X, paths(d=2), rbf) == _lib.SK_ERR_SHAPE
     assert call_lifted(fn, X, X, rbf, ws=None) == _lib.SK_ERR_WORKSPACE
