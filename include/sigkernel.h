@@ -85,6 +85,14 @@ typedef struct sk_paths {
  * Precision: path points and outputs are float32; the increments and their
  * inner products are formed in float32 (FMA), and the sweep state -- every
  * node value of the scheme -- is IEEE double.
+ *
+ * Channels: any dim >= 1 for sigkernel_pair / sigkernel_gram / sigkernel_mmd2
+ * values.  Up to 16 channels the sweeps form the inner products on the fly
+ * from increments held in registers; wider batches form the increment Gram
+ * on the matrix cores first (float32 sums) and sweep from it, with x paths
+ * of at most 2048 fine rows (2^lambda (x.len - 1) <= 2048; else
+ * SK_ERR_UNSUPPORTED).  Gradients (sigkernel_gram_backward, the MMD
+ * gradient), the lifted kernels and the corrector take at most 16 channels.
  */
 
 /* flags */

@@ -164,9 +164,57 @@ PairLayout pair_layout(const sk_paths* X0, const sk_paths* Y0, int32_t lam0, boo
   return L;
 }
 
+// Channels beyond which the fused sweeps are not compiled: wider batches run
+// the coefficient sweep (coef.hip) with the increment Gram formed first.
+constexpr int32_t kMaxFusedDim = 16;
+// Coefficient slots held at once (waves are launched in chunks within it).
+constexpr size_t kCoefCapBytes = size_t(1) << 30;
+
+struct CoefPlan {
+  int R;
+  int32_t lam, rep;
+  int32_t run;
+  int64_t runs_per_row, n_waves;
+  int64_t stride;  // floats per wave
+  int64_t chunk;   // waves per producer / sweep launch pair
+  size_t coef_off, total;
+};
+
+// mode 0: pairs; 1, 2: Gram (2: upper triangle)
+CoefPlan coef_plan(const sk_paths* X, const sk_paths* Y, int32_t lam0, int mode) {
+  CoefPlan P{};
+  const Order o = split_order(lam0);
+  const sk_paths Xr = refined(X, o.rep), Yr = refined(Y, o.rep);
+  P.lam = o.k;
+  P.rep = o.rep;
+  const int64_t fine_rows = (int64_t)(Xr.len > 1 ? Xr.len - 1 : 1) << o.k;
+  P.R = sk::coef_rows_per_lane(fine_rows, o.k);
+  P.coef_off = forward_ws(X, Y);  // unrefined increments and plans
+  P.total = P.coef_off;
+  if (P.R == 0) return P;
+  if (mode == 0) {
+    P.run = 1;
+    P.runs_per_row = 1;
+    P.n_waves = X->n_paths;
+  } else {
+    P.run = Y->offsets ? 1 : (int32_t)choose_run(X->n_paths, Y->n_paths, 0);
+    P.runs_per_row = (Y->n_paths + P.run - 1) / P.run;
+    P.n_waves = X->n_paths * P.runs_per_row;
+  }
+  const int64_t cols = (int64_t)P.run * (Yr.len > 1 ? Yr.len - 1 : 1);
+  P.stride = sk::coef_wave_floats(cols, P.R, o.k);
+  P.chunk = (int64_t)(kCoefCapBytes / ((size_t)P.stride * sizeof(float)));
+  if (P.chunk < 1) P.chunk = 1;
+  if (P.chunk > P.n_waves) P.chunk = P.n_waves > 0 ? P.n_waves : 1;
+  P.total = P.coef_off + align256((size_t)P.chunk * (size_t)P.stride * sizeof(float));
+  return P;
+}
+
 // Workspace of a Gram call: the one-wave sweep's layout or, for x paths too
-// tall for it, the persistent pair kernel's.
+// tall for it, the persistent pair kernel's; the coefficient sweep's for
+// batches wider than the fused sweeps.
 size_t gram_ws(const sk_paths* X, const sk_paths* Y, int32_t lam) {
+  if (X->dim > kMaxFusedDim && X->dim == Y->dim) return coef_plan(X, Y, lam, 1).total;
   const Order o = split_order(lam);
   const sk_paths Xr = refined(X, o.rep), Yr = refined(Y, o.rep);
   const size_t f = forward_ws(&Xr, &Yr);
@@ -326,8 +374,101 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam0, float* o
   return e == hipSuccess ? SK_OK : SK_ERR_HIP;
 }
 
+// Any channel count: the increment Gram on the matrix cores, then the
+// coefficient sweep, wave chunk by wave chunk (coef.hip).
+sk_status run_coef(const sk_paths* X, const sk_paths* Y, int32_t lam0, uint32_t flags,
+                   float* out, void* ws, size_t ws_bytes, hipStream_t stream, int mode) {
+  const CoefPlan P = coef_plan(X, Y, lam0, mode);
+  if (P.R == 0) return SK_ERR_UNSUPPORTED;
+  if (ws_bytes < P.total) return SK_ERR_WORKSPACE;
+  const int d = X->dim;
+  const int dp = sk::padded_dim(d);
+  const ForwardLayout L = forward_layout(X, Y);
+  char* base = static_cast<char*>(ws);
+  float* incx = reinterpret_cast<float*>(base + L.incx) + sk::kStreamPad * dp;
+  float* incy = reinterpret_cast<float*>(base + L.incy) + sk::kStreamPad * dp;
+  float* coef = reinterpret_cast<float*>(base + P.coef_off);
+  sk::PathPlan px{reinterpret_cast<int32_t*>(base + L.planx_n),
+                  reinterpret_cast<int64_t*>(base + L.planx_start)};
+  sk::PathPlan py{reinterpret_cast<int32_t*>(base + L.plany_n),
+                  reinterpret_cast<int64_t*>(base + L.plany_start)};
+  const sk::Batch bx = to_batch(X), by = to_batch(Y);
+  if (X->offsets && sk::launch_plan(bx, px, stream) != hipSuccess) return SK_ERR_HIP;
+  if (Y->offsets && sk::launch_plan(by, py, stream) != hipSuccess) return SK_ERR_HIP;
+  const int rounding = rounding_of(flags);
+  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, 1.0f, dp, incx, stream, rounding) !=
+      hipSuccess)
+    return SK_ERR_HIP;
+  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream, rounding) !=
+      hipSuccess)
+    return SK_ERR_HIP;
+  // both kernels see the refined counts (the producer divides them back)
+  if (X->offsets && sk::launch_scale_plan(px, X->n_paths, P.rep, stream) != hipSuccess)
+    return SK_ERR_HIP;
+  if (Y->offsets && sk::launch_scale_plan(py, Y->n_paths, P.rep, stream) != hipSuccess)
+    return SK_ERR_HIP;
+  const sk_paths Xr = refined(X, P.rep), Yr = refined(Y, P.rep);
+
+  sk::CoefArgs c{};
+  c.incx = incx;
+  c.incy = incy;
+  c.x_n = X->offsets ? px.n : nullptr;
+  c.x_start = X->offsets ? px.start : nullptr;
+  c.y_n = Y->offsets ? py.n : nullptr;
+  c.y_start = Y->offsets ? py.start : nullptr;
+  c.x_len = Xr.len;
+  c.y_len = Yr.len;
+  c.nx = X->n_paths;
+  c.ny = Y->n_paths;
+  c.mode = mode;
+  c.run = P.run;
+  c.runs_per_row = P.runs_per_row;
+  c.d = d;
+  c.dpad = dp;
+  c.R = P.R;
+  c.lam = P.lam;
+  c.rep = P.rep;
+  c.scale = ldexpf(1.0f, -(2 * P.lam + 1)) / ((float)P.rep * (float)P.rep);
+  c.coef = coef;
+  c.coef_stride = P.stride;
+
+  sk::SweepArgs a{};
+  a.x_n = c.x_n;
+  a.x_start = c.x_start;
+  a.y_n = c.y_n;
+  a.y_start = c.y_start;
+  a.x_len = Xr.len;
+  a.y_len = Yr.len;
+  a.nx = X->n_paths;
+  a.ny = Y->n_paths;
+  a.mode = mode;
+  a.no_diag = (flags & SK_NO_DIAG) ? 1 : 0;
+  a.implicit = (flags & SK_IMPLICIT) ? 1 : 0;
+  a.run = P.run;
+  a.runs_per_row = P.runs_per_row;
+  a.out = out;
+  a.out_ld = Y->n_paths;
+  a.coef = coef;
+  a.coef_stride = P.stride;
+  for (int64_t w0 = 0; w0 < P.n_waves; w0 += P.chunk) {
+    const int64_t nw = (P.n_waves - w0) < P.chunk ? (P.n_waves - w0) : P.chunk;
+    c.wave0 = w0;
+    c.n_waves = nw;
+    if (sk::launch_coef(c, rounding, X->len - 1, Y->len - 1, stream) != hipSuccess)
+      return SK_ERR_HIP;
+    a.wave0 = w0;
+    a.n_waves = nw;
+    const hipError_t e = sk::launch_coef_sweep(a, P.lam, P.R, a.implicit != 0, stream);
+    if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;
+    if (e != hipSuccess) return SK_ERR_HIP;
+  }
+  return SK_OK;
+}
+
 sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam0, uint32_t flags,
                       float* out, void* ws, size_t ws_bytes, hipStream_t stream, int mode) {
+  if (X->dim > kMaxFusedDim)
+    return run_coef(X, Y, lam0, flags, out, ws, ws_bytes, stream, mode);
   const int rounding = rounding_of(flags);
   const sk_tune tune = sk::tuning_for(mode == 0 ? SK_OP_PAIR : SK_OP_GRAM, X, Y, lam0, flags);
   const bool implicit = (flags & SK_IMPLICIT) != 0;
@@ -673,6 +814,7 @@ size_t sigkernel_workspace_bytes(int32_t op, const sk_paths* X, const sk_paths* 
   switch (op) {
     case SK_OP_PAIR:
       if (X->dim != Y->dim) return 0;
+      if (X->dim > kMaxFusedDim) return coef_plan(X, Y, dyadic_order, 0).total;
       return pair_layout(X, Y, dyadic_order, false).total;
     case SK_OP_GRAM:
       return gram_ws(X, Y, dyadic_order);

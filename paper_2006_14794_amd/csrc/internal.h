@@ -159,6 +159,38 @@ hipError_t launch_pair_plan(const PairPlanArgs& p, hipStream_t stream);
 hipError_t launch_pairs(const PairArgs& a, int lam, int rows_per_lane, int dim,
                         int64_t max_waves, hipStream_t stream, int blocks_per_cu = 0);
 
+// Coefficient-driven sweep for any number of channels (coef.hip).
+// coef_kernel writes the pre-scaled coarse coefficients of the launched
+// waves in the order coef_sweep_kernel reads them; see coef.hip.
+struct CoefArgs {
+  const float* incx;        // dense unscaled increments (not refined)
+  const float* incy;
+  const int32_t* x_n;       // plans of the batch as swept (refined: n rep, start rep)
+  const int64_t* x_start;
+  const int32_t* y_n;
+  const int64_t* y_start;
+  int32_t x_len, y_len;     // points per path as swept (refined)
+  int64_t nx, ny;
+  int32_t mode;             // as SweepArgs
+  int32_t run;
+  int64_t runs_per_row;
+  int64_t wave0, n_waves;   // waves of this launch
+  int32_t d, dpad;
+  int32_t R, lam, rep;      // the consuming sweep's rows per lane and order; refinement
+  float scale;              // 2^-(2 lam + 1) / rep^2
+  float* coef;              // per launched wave: coef_stride floats
+  int64_t coef_stride;
+};
+// Rows per lane of the coefficient sweep (R >= 2^lam; 0 if none fits).
+int coef_rows_per_lane(int64_t fine_rows, int lam);
+// Floats of one wave's coefficient slots for a run of total_cols columns.
+int64_t coef_wave_floats(int64_t total_cols, int R, int lam);
+// max_m, max_n: unrefined increment counts (upper bounds) of the batches.
+hipError_t launch_coef(const CoefArgs& a, int precision, int64_t max_m, int64_t max_n,
+                       hipStream_t stream);
+hipError_t launch_coef_sweep(const SweepArgs& a, int lam, int rows_per_lane, bool implicit,
+                             hipStream_t stream, int waves_per_block = 0);
+
 // Increment Gram of uniform batches on the matrix cores (gram_mfma.hip).
 struct GramArgs {
   const float* x;           // points [nx][x_len][d]

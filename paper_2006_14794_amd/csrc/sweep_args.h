@@ -34,6 +34,10 @@ struct SweepArgs {
   // adjoint support: per wave, nsteps x 64 lanes x (R 2^lam) floats
   float* store;
   int64_t store_stride;
+  // coefficient sweep: per launched wave, coef_stride floats of pre-scaled
+  // coarse coefficients in step order ([step][lane][coarse row of the strip])
+  const float* coef;
+  int64_t coef_stride;
 };
 
 // Rows before and after the data of every dense increment buffer: a wave
