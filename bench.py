@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--cpu-sample-pairs", type=int, default=0,
                     help="pairs of the workload timed on the CPU oracle (0: all)")
     ap.add_argument("--workload", choices=["gram", "mmd", "ragged", "increment_gram", "corrector",
-                                           "lifted"],
+                                           "lifted", "fig3"],
                     default="gram",
                     help="gram: the 128 x 128 Gram batch (default, the reported metric); "
                          "mmd: unbiased MMD^2 of 64 vs 64 512-point paths with its gradient; "
@@ -60,7 +60,9 @@ def parse():
                          "increment_gram: the coarse Gram of the Gram batch on the matrix cores; "
                          "corrector: order-3 values of 65536 held-out pairs by the learned "
                          "corrector with fallback, against the plain order-3 solve; "
-                         "lifted: the RBF-lifted Gram (sigma 0.5) of the Gram batch")
+                         "lifted: the RBF-lifted Gram (sigma 0.5) of the Gram batch; "
+                         "fig3: the Figure 3 protocol (time to reach 1e-3 of a P5 target on 5 "
+                         "Brownian pairs, against length and against channels)")
     return ap.parse_args()
 
 
@@ -72,7 +74,9 @@ def sweep_ops_per_cell(d: int, lam: int) -> float:
     return 2.0 + 0.5 * d / float(4 ** lam)
 
 
-SWEEP_SOURCES = ("sweep_fwd_kernel.h", "sweep_inst.h", "dispatch.h", "internal.h")
+# the files the Gram sweep kernel compiles from (its translation unit and headers)
+SWEEP_SOURCES = ("sweep_k0_l1.hip", "sweep_inst.h", "dispatch.h", "sweep_fwd_kernel.h",
+                 "sweep_args.h")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pmc_traffic_sweep_kernel_gram128_L256_d9_lam1.md")
 
 
@@ -356,6 +360,79 @@ def bench_lifted(args):
     print(json.dumps(rec), flush=True)
 
 
+FIG3_LENGTHS = (10, 20, 50, 100, 200, 500, 1000, 2000)
+FIG3_DIMS = (2, 8, 32, 128, 512, 2048)
+
+
+def bench_fig3(args):
+    """The performance experiment of Figure 3: for N = 5 pairs of Brownian
+    paths, the smallest dyadic order whose values lie within 1e-3 of the
+    order-5 values (the P5 target) on every pair, and the time of the
+    solve at that order -- on the GPU, and for the FP64 oracle on the host --
+    against the length (d = 2) and against the channels (length 10).  The
+    fitted exponents of time against length show how each side scales."""
+    import torch
+    import paper_2006_14794_amd as sk
+    import workloads
+    n_pairs, acc, target_order = 5, 1e-3, 5
+    configs = [(L, 2) for L in FIG3_LENGTHS] + [(10, d) for d in FIG3_DIMS if d != 2]
+    rows = []
+    for L, d in configs:
+        X, Y = workloads.fig3_pairs(L, d, n_pairs)
+        Xt, Yt = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+        target = sk.sigkernel_pair(Xt, Yt, target_order).cpu().numpy().astype(np.float64)
+        lam = target_order
+        for cand in range(target_order):
+            v = sk.sigkernel_pair(Xt, Yt, cand).cpu().numpy().astype(np.float64)
+            if np.all(np.abs(v - target) <= acc):
+                lam = cand
+                break
+        graph, _ = sk.capture_pair(Xt, Yt, lam)
+        reps = 20
+        per, _ = time_steps(graph.replay, reps, 3)
+        row = {"length": L, "dim": d, "order": lam, "gpu_ms": float(np.mean(per))}
+        if not args.no_cpu_baseline:
+            import oracle
+            xs, ys = X.astype(np.float64), Y.astype(np.float64)
+            oracle.pairs(xs[:1], ys[:1], 0)
+            t0 = time.perf_counter()
+            ref = oracle.pairs(xs, ys, lam, nthreads=oracle.max_threads())
+            row["cpu_ms"] = (time.perf_counter() - t0) * 1e3
+            got = sk.sigkernel_pair(Xt, Yt, lam).cpu().numpy()
+            row["gpu_err_vs_oracle"] = float(np.max(np.abs(got - ref) / np.maximum(1, np.abs(ref))))
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+
+    def exponent(key):
+        pts = [(r["length"], r[key]) for r in rows if r["dim"] == 2 and r["length"] >= 100
+               and key in r]
+        if len(pts) < 2:
+            return None
+        lx = np.log([p[0] for p in pts])
+        ly = np.log([p[1] for p in pts])
+        return float(np.polyfit(lx, ly, 1)[0])
+
+    longest = [r for r in rows if r["dim"] == 2][-1]
+    rec = {
+        "metric": "time to reach 1e-3 of the P5 target, 5 Brownian pairs (Figure 3 protocol)",
+        "value": longest["gpu_ms"], "unit": "ms", "n_gpus": 1, "steps": 20, "warmup": 3,
+        "ms_per_step": longest["gpu_ms"], "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"Figure 3 protocol: 5 Brownian pairs; value at length "
+                               f"{longest['length']}, d=2", "pairs": n_pairs,
+                   "accuracy": acc, "target_order": target_order},
+        "sweep": rows,
+        "time_vs_length_exponent": {"gpu": exponent("gpu_ms"), "cpu_oracle": exponent("cpu_ms")},
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = {"value": longest["cpu_ms"], "unit": "ms",
+                               "cores": min(n_pairs, __import__("oracle").max_threads()),
+                               "kind": "oracle",
+                               "sample": f"the same 5 pairs at length {longest['length']}, "
+                                         "OpenMP over the pairs"}
+    print(json.dumps(rec), flush=True)
+
+
 def bench_increment_gram(args):
     """The coarse increment Gram G0 of the 128 x 128 Gram batch (255 x 255 per
     pair, d = 9) on the matrix cores, written to HBM: bound by the 4-byte
@@ -477,6 +554,9 @@ def main():
         return
     if args.workload == "lifted":
         bench_lifted(args)
+        return
+    if args.workload == "fig3":
+        bench_fig3(args)
         return
 
     import torch

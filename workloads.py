@@ -146,3 +146,19 @@ def random_paths(seed: int, n_paths: int, n_points: int, dim: int,
 
 def ragged_lengths(seed: int, n: int, lo: int, hi: int) -> np.ndarray:
     return _rng(seed).integers(lo, hi + 1, size=n)
+
+
+# 6 -------------------------------------------------------------------------
+SEED_FIG3 = 14800
+
+
+def fig3_pairs(n_points: int, dim: int, n_pairs: int = 5, seed: int = SEED_FIG3):
+    """(X, Y) [n_pairs, n_points, dim]: Brownian motion on [0, 1] sampled at
+    n_points equally spaced times, start 0, each channel with variance 1/dim
+    at time 1 (increments N(0, 1 / (dim (n_points - 1)))), so that |x_1|^2 has
+    mean 1 for every dim -- the inputs of the Figure 3 protocol."""
+    rng = _rng(seed + 1000 * dim + n_points)
+    std = 1.0 / np.sqrt(dim * (n_points - 1))
+    X = brownian(rng, n_pairs, n_points, dim, std)
+    Y = brownian(rng, n_pairs, n_points, dim, std)
+    return X, Y
