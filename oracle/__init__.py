@@ -31,6 +31,9 @@ Contents
   ``solve_coef`` (either scheme driven by a given coefficient matrix),
   ``solve_lifted`` and the OpenMP batches ``lifted_rbf_pairs`` /
   ``lifted_rbf_gram``.
+* ``reduced_measure``: the moments-matching reduction of a discrete measure on
+  paths (eqs. (min_lasso), (fixed_point)): soft-thresholding, proximal
+  gradient, and the penalty that gives a chosen support size.
 
 Every function here is pinned by ``tests/test_oracle_pins.py`` against
 something other than itself (hand-derived values, closed forms, library

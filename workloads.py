@@ -162,3 +162,28 @@ def fig3_pairs(n_points: int, dim: int, n_pairs: int = 5, seed: int = SEED_FIG3)
     X = brownian(rng, n_pairs, n_points, dim, std)
     Y = brownian(rng, n_pairs, n_points, dim, std)
     return X, Y
+
+
+# 7 -------------------------------------------------------------------------
+SEED_FBM = 14801
+
+
+def fbm_paths(seed: int = SEED_FBM, n_paths: int = 30, n_points: int = 100,
+              hursts=(0.2, 0.5, 0.8)):
+    """(paths [n_paths, n_points, 2], hurst [n_paths]): fractional Brownian
+    motion on t_i = i / (n_points - 1), B(0) = 0, with a Hurst exponent drawn
+    uniformly from `hursts` per path, sampled exactly through the Cholesky
+    factor of its covariance 0.5 (s^{2H} + t^{2H} - |t - s|^{2H}); channel 0
+    is the time t, channel 1 the fBM."""
+    rng = _rng(seed)
+    t = np.linspace(0.0, 1.0, n_points)
+    H = rng.choice(np.asarray(hursts, dtype=np.float64), size=n_paths)
+    out = np.zeros((n_paths, n_points, 2), dtype=np.float64)
+    out[:, :, 0] = t
+    s, u = np.meshgrid(t[1:], t[1:], indexing="ij")
+    for i in range(n_paths):
+        h2 = 2.0 * H[i]
+        cov = 0.5 * (s ** h2 + u ** h2 - np.abs(s - u) ** h2)
+        L = np.linalg.cholesky(cov)
+        out[i, 1:, 1] = L @ rng.normal(size=n_points - 1)
+    return out.astype(np.float32), H
