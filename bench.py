@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--cpu-sample-pairs", type=int, default=0,
                     help="pairs of the workload timed on the CPU oracle (0: all)")
     ap.add_argument("--workload", choices=["gram", "mmd", "ragged", "increment_gram", "corrector",
-                                           "lifted", "fig3"],
+                                           "lifted", "fig3", "reduce"],
                     default="gram",
                     help="gram: the 128 x 128 Gram batch (default, the reported metric); "
                          "mmd: unbiased MMD^2 of 64 vs 64 512-point paths with its gradient; "
@@ -62,7 +62,8 @@ def parse():
                          "corrector with fallback, against the plain order-3 solve; "
                          "lifted: the RBF-lifted Gram (sigma 0.5) of the Gram batch; "
                          "fig3: the Figure 3 protocol (time to reach 1e-3 of a P5 target on 5 "
-                         "Brownian pairs, against length and against channels)")
+                         "Brownian pairs, against length and against channels); "
+                         "reduce: the reduced measure of 30 fBM paths (support 6)")
     return ap.parse_args()
 
 
@@ -433,6 +434,63 @@ def bench_fig3(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_reduce(args):
+    """The reduced-measure experiment: 30 fBM paths (Hurst exponent drawn from
+    {0.2, 0.5, 0.8}, 50 points, time channel), their symmetric signature Gram
+    at dyadic order 6, and the penalty of eq. (min_lasso) for a support of 6
+    found by 40 bisection rounds of 3000 proximal-gradient iterations."""
+    import torch
+    import paper_2006_14794_amd as sk
+    import workloads
+    lam_order, support, iters, rounds = 6, 6, 3000, 40
+    P, H = workloads.fbm_paths(n_points=50)
+    Pt = torch.from_numpy(P).cuda()
+    K = sk.sigkernel_gram(Pt, None, lam_order, symmetric=True)
+
+    def gram_step():
+        sk.sigkernel_gram(Pt, None, lam_order, symmetric=True, out=K)
+    per_g, wall_g = time_steps(gram_step, args.steps, args.warmup)
+    res = {}
+
+    def search_step():
+        res["r"] = sk.reduced_measure_support(K, support, iters, rounds)
+    per_s, wall_s = time_steps(search_step, max(1, args.steps // 4), 1)
+    beta, lam, step = res["r"]
+    b = beta.cpu().numpy()
+    nz = np.nonzero(b)[0]
+    ms = (wall_g / args.steps + wall_s / max(1, args.steps // 4)) * 1e3
+    total_iters = iters * rounds
+    rec = {
+        "metric": "reduced measure of 30 fBM paths: signature Gram + support search time",
+        "value": ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "30 fBM paths (H in {0.2,0.5,0.8}), 50 points + time, "
+                               "dyadic order 6, support 6", "iters_per_round": iters,
+                   "rounds": rounds},
+        "gram_ms": float(np.mean(per_g)), "search_ms": float(np.mean(per_s)),
+        "us_per_iteration": float(np.mean(per_s)) * 1e3 / total_iters,
+        "selected": {"paths": nz.tolist(), "hurst": H[nz].tolist(),
+                     "weights": b[nz].tolist(), "lam": lam.item(), "step": step.item()},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import reduced_measure as rm
+        t0 = time.perf_counter()
+        Kr = oracle.gram(P.astype(np.float64), P.astype(np.float64), lam_order,
+                         nthreads=oracle.max_threads())
+        tg = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rb, rl = rm.ista_support(Kr, np.full(30, 1.0 / 30), support, iters, rounds)
+        ts = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": (tg + ts) * 1e3, "unit": "ms",
+                               "cores": oracle.max_threads(), "kind": "oracle",
+                               "sample": f"the whole experiment: Gram {tg * 1e3:.0f} ms (all "
+                                         f"threads), search {ts * 1e3:.0f} ms (numpy)",
+                               "selected_paths": np.nonzero(rb)[0].tolist(), "lam": rl}
+    print(json.dumps(rec), flush=True)
+
+
 def bench_increment_gram(args):
     """The coarse increment Gram G0 of the 128 x 128 Gram batch (255 x 255 per
     pair, d = 9) on the matrix cores, written to HBM: bound by the 4-byte
@@ -557,6 +615,9 @@ def main():
         return
     if args.workload == "fig3":
         bench_fig3(args)
+        return
+    if args.workload == "reduce":
+        bench_reduce(args)
         return
 
     import torch

@@ -239,6 +239,41 @@ sk_status sigkernel_gram_lifted(const sk_paths *X, const sk_paths *Y, int32_t dy
                                 uint32_t flags, const sk_static_kernel *kernel, float *K,
                                 void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Reduced measures (Section "Moments-matching reduction algorithm for the
+ * support of a discrete measure on paths").  For a measure
+ * mu = sum_i alpha_i delta_{x_i} and the signature-kernel Gram
+ * K[i][j] = k(x_i, x_j) (e.g. from sigkernel_gram with SK_SYMMETRIC), the
+ * weights beta of the reduced measure minimise eq. (min_lasso),
+ *   f(beta) = (alpha - beta)^T K (alpha - beta) + lam |beta|_1,
+ * by the proximal-gradient iteration of eq. (fixed_point) started at
+ * beta = alpha:
+ *   beta <- A_t(beta - step 2 K (beta - alpha)),  A_t soft-thresholding,
+ * with t = step * lam (the proximal map of step lam |.|_1; the printed
+ * iteration writes the threshold as the step itself).
+ *  - K: DEVICE float[n][n] (symmetric), alpha: DEVICE float[n]; 1 <= n <= 4096.
+ *  - step > 0: used as given; step == 0: 1 / (2 * 1.05 * rho), rho the
+ *    largest |eigenvalue| of K by power iteration (200 steps).  step_out:
+ *    DEVICE double[1] receiving the step used, or NULL.
+ *  - beta: DEVICE double[n] (overwritten).  One workgroup; iterations are
+ *    matrix-vector products summed in double.
+ *  - SK_ERR_VALUE: lam < 0, step < 0 or not finite.
+ */
+/* Fixed penalty: `iters` iterations; loss (DEVICE double[iters + 1] or NULL)
+ * receives f before each iteration and after the last. */
+sk_status sigkernel_reduced_measure(const float *K, const float *alpha, int32_t n, double lam,
+                                    double step, int32_t iters, double *beta, double *loss,
+                                    double *step_out, void *stream);
+/* Support size: `rounds` bisection steps on lam over [0, 2 max_i |(K alpha)_i|]
+ * (beyond that beta = 0 is optimal); each round runs `iters` iterations from
+ * the previous round's beta; more non-zeros than `support` raises the lower
+ * end, otherwise the upper.  beta and lam_out (DEVICE double[1]) receive the
+ * last round whose support size equals `support`, else the last round. */
+sk_status sigkernel_reduced_measure_support(const float *K, const float *alpha, int32_t n,
+                                            int32_t support, int32_t iters, int32_t rounds,
+                                            double step, double *beta, double *lam_out,
+                                            double *step_out, void *stream);
+
 /* Workspace sizing.  op is one of the SK_OP_* values. */
 enum { SK_OP_PAIR = 0, SK_OP_GRAM = 1, SK_OP_GRAM_BACKWARD = 2, SK_OP_MMD2 = 3,
        SK_OP_CORRECTOR_FEATURES = 4,  /* X, Y: the pairs                              */

@@ -11,7 +11,7 @@ from ._lib import SK_NO_DIAG, SK_SYMMETRIC, SigKernelError, load, status_string,
 from .api import (RaggedPaths, SigKernelGram, SigKernelGramSymmetric, SigKernelMMD2, gram, mmd2,
                   sigkernel_gram, sigkernel_gram_backward, sigkernel_increment_gram, sigkernel_mmd2,
                   sigkernel_gram_lifted, sigkernel_pair, sigkernel_pair_lifted,
-                  workspace_bytes)
+                  reduced_measure, reduced_measure_support, workspace_bytes)
 from . import corrector
 from .corrector import Corrector
 from .graph import CapturedCalls, capture_gram, capture_mmd2, capture_pair
@@ -22,6 +22,7 @@ __all__ = [
     "SigKernelMMD2", "mmd2", "sigkernel_mmd2", "sigkernel_increment_gram",
     "sigkernel_gram", "sigkernel_gram_backward", "sigkernel_pair",
     "sigkernel_gram_lifted", "sigkernel_pair_lifted",
+    "reduced_measure", "reduced_measure_support",
     "status_string", "version", "workspace_bytes",
     "SK_SYMMETRIC", "SK_NO_DIAG",
     "Corrector", "corrector",

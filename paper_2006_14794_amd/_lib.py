@@ -76,6 +76,8 @@ EXPORTED = (
     "sigkernel_corrector_predict",
     "sigkernel_pair_lifted",
     "sigkernel_gram_lifted",
+    "sigkernel_reduced_measure",
+    "sigkernel_reduced_measure_support",
 )
 
 
@@ -147,6 +149,12 @@ def load():
     lib.sigkernel_pair.restype = i32
     lib.sigkernel_gram.argtypes = [P, P, i32, u32, vp, vp, sz, vp]
     lib.sigkernel_gram.restype = i32
+    dbl = ctypes.c_double
+    lib.sigkernel_reduced_measure.argtypes = [vp, vp, i32, dbl, dbl, i32, vp, vp, vp, vp]
+    lib.sigkernel_reduced_measure.restype = i32
+    lib.sigkernel_reduced_measure_support.argtypes = [vp, vp, i32, i32, i32, i32, dbl, vp, vp,
+                                                      vp, vp]
+    lib.sigkernel_reduced_measure_support.restype = i32
     SKp = ctypes.POINTER(SkStaticKernel)
     for name in ("sigkernel_pair_lifted", "sigkernel_gram_lifted"):
         getattr(lib, name).argtypes = [P, P, i32, u32, SKp, vp, vp, sz, vp]

@@ -243,6 +243,54 @@ def sigkernel_gram_lifted(X: PathsLike, Y: Optional[PathsLike] = None, dyadic_or
     return out
 
 
+def _reduce_inputs(K: torch.Tensor, alpha: Optional[torch.Tensor]):
+    if K.dim() != 2 or K.shape[0] != K.shape[1] or not K.is_cuda:
+        raise ValueError("K must be a square device tensor")
+    K = K.to(torch.float32).contiguous()
+    n = K.shape[0]
+    if alpha is None:
+        alpha = torch.full((n,), 1.0 / n, dtype=torch.float32, device=K.device)
+    alpha = alpha.to(device=K.device, dtype=torch.float32).contiguous()
+    if alpha.numel() != n:
+        raise ValueError("alpha must have one weight per row of K")
+    return K, alpha, n
+
+
+def reduced_measure(K: torch.Tensor, lam: float, iters: int, *,
+                    alpha: Optional[torch.Tensor] = None, step: float = 0.0):
+    """(beta, loss, step): `iters` proximal-gradient iterations of eq.
+    (fixed_point) for eq. (min_lasso) from beta = alpha (default uniform
+    weights), on the GPU.  loss[k] is the objective before iteration k and
+    after the last; step 0 chooses 1 / (2 * 1.05 * |K|_2)."""
+    lib = _lib.load()
+    K, alpha, n = _reduce_inputs(K, alpha)
+    beta = torch.empty(n, dtype=torch.float64, device=K.device)
+    loss = torch.empty(iters + 1, dtype=torch.float64, device=K.device)
+    step_out = torch.empty(1, dtype=torch.float64, device=K.device)
+    st = lib.sigkernel_reduced_measure(K.data_ptr(), alpha.data_ptr(), n, float(lam),
+                                       float(step), int(iters), beta.data_ptr(), loss.data_ptr(),
+                                       step_out.data_ptr(), _stream_ptr(K.device))
+    _lib.check(st, "sigkernel_reduced_measure")
+    return beta, loss, step_out
+
+
+def reduced_measure_support(K: torch.Tensor, support: int, iters: int = 3000, rounds: int = 40,
+                            *, alpha: Optional[torch.Tensor] = None, step: float = 0.0):
+    """(beta, lam, step): the penalty found by bisection so that the reduced
+    measure has `support` atoms, and its weights (GPU)."""
+    lib = _lib.load()
+    K, alpha, n = _reduce_inputs(K, alpha)
+    beta = torch.empty(n, dtype=torch.float64, device=K.device)
+    lam = torch.empty(1, dtype=torch.float64, device=K.device)
+    step_out = torch.empty(1, dtype=torch.float64, device=K.device)
+    st = lib.sigkernel_reduced_measure_support(K.data_ptr(), alpha.data_ptr(), n, int(support),
+                                               int(iters), int(rounds), float(step),
+                                               beta.data_ptr(), lam.data_ptr(),
+                                               step_out.data_ptr(), _stream_ptr(K.device))
+    _lib.check(st, "sigkernel_reduced_measure_support")
+    return beta, lam, step_out
+
+
 def sigkernel_gram_backward(X: torch.Tensor, Y: Optional[torch.Tensor], dK: torch.Tensor,
                             dyadic_order: int = 0, *, symmetric: bool = False,
                             no_diag: bool = False, need_x: bool = True, need_y: bool = True,

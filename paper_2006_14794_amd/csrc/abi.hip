@@ -925,6 +925,51 @@ sk_status sigkernel_gram_lifted(const sk_paths* X, const sk_paths* Y, int32_t dy
                     static_cast<hipStream_t>(stream), (flags & SK_SYMMETRIC) ? 2 : 1);
 }
 
+sk_status sigkernel_reduced_measure(const float* K, const float* alpha, int32_t n, double lam,
+                                    double step, int32_t iters, double* beta, double* loss,
+                                    double* step_out, void* stream) {
+  if (!K || !alpha || !beta) return SK_ERR_NULL;
+  if (n < 1 || n > sk::kMaxReduceN || iters < 0) return SK_ERR_SHAPE;
+  if (!(lam >= 0.0) || !isfinite(lam) || !(step >= 0.0) || !isfinite(step)) return SK_ERR_VALUE;
+  sk::ReduceArgs a{};
+  a.K = K;
+  a.ld = n;
+  a.alpha = alpha;
+  a.n = n;
+  a.lam = lam;
+  a.step = step;
+  a.iters = iters;
+  a.beta = beta;
+  a.loss = loss;
+  a.step_out = step_out;
+  return sk::launch_reduce(a, static_cast<hipStream_t>(stream)) == hipSuccess ? SK_OK
+                                                                               : SK_ERR_HIP;
+}
+
+sk_status sigkernel_reduced_measure_support(const float* K, const float* alpha, int32_t n,
+                                            int32_t support, int32_t iters, int32_t rounds,
+                                            double step, double* beta, double* lam_out,
+                                            double* step_out, void* stream) {
+  if (!K || !alpha || !beta || !lam_out) return SK_ERR_NULL;
+  if (n < 1 || n > sk::kMaxReduceN || iters < 0) return SK_ERR_SHAPE;
+  if (support < 1 || support > n || rounds < 1) return SK_ERR_VALUE;
+  if (!(step >= 0.0) || !isfinite(step)) return SK_ERR_VALUE;
+  sk::ReduceArgs a{};
+  a.K = K;
+  a.ld = n;
+  a.alpha = alpha;
+  a.n = n;
+  a.step = step;
+  a.iters = iters;
+  a.support = support;
+  a.rounds = rounds;
+  a.beta = beta;
+  a.lam_out = lam_out;
+  a.step_out = step_out;
+  return sk::launch_reduce(a, static_cast<hipStream_t>(stream)) == hipSuccess ? SK_OK
+                                                                               : SK_ERR_HIP;
+}
+
 sk_status sigkernel_increment_gram(const sk_paths* X, const sk_paths* Y, int32_t gram,
                                   uint32_t flags, float* G0, void* stream) {
   if (!X || !Y) return SK_ERR_NULL;

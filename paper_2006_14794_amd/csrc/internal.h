@@ -191,6 +191,23 @@ hipError_t launch_coef(const CoefArgs& a, int precision, int64_t max_m, int64_t 
 hipError_t launch_coef_sweep(const SweepArgs& a, int lam, int rows_per_lane, bool implicit,
                              hipStream_t stream, int waves_per_block = 0);
 
+// Reduced measure by proximal gradient (reduce.hip): one workgroup.
+constexpr int kMaxReduceN = 4096;
+struct ReduceArgs {
+  const float* K;           // [n][ld] Gram, row-major
+  int64_t ld;
+  const float* alpha;       // [n] weights of the measure
+  int32_t n;
+  double lam, step;         // penalty (fixed-penalty mode); step <= 0: automatic
+  int32_t iters;            // iterations (per bisection round in support mode)
+  int32_t support, rounds;  // support > 0: bisection on the penalty for this support size
+  double* beta;             // [n] out
+  double* loss;             // [iters + 1] out (fixed-penalty mode; nullable)
+  double* lam_out;          // [1] out (support mode)
+  double* step_out;         // [1] out, nullable
+};
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream);
+
 // Increment Gram of uniform batches on the matrix cores (gram_mfma.hip).
 struct GramArgs {
   const float* x;           // points [nx][x_len][d]

@@ -205,3 +205,20 @@ def test_lifted_workspace_covers_both_static_kernels():
         # node rows of both batches (padded to 4 channels, 128 rows each side)
         nodes = (5 * 40 + 256) * 4 * 4 + ((5 if op == 7 else 7) * (40 if op == 7 else 30) + 256) * 16
         assert b >= max(p, nodes)
+
+
+def test_reduced_measure_argument_errors():
+    lib = _lib.load()
+    f = lib.sigkernel_reduced_measure
+    g = lib.sigkernel_reduced_measure_support
+    assert f(None, FAKE, 5, 0.1, 0.0, 10, FAKE, None, None, None) == _lib.SK_ERR_NULL
+    assert f(FAKE, FAKE, 0, 0.1, 0.0, 10, FAKE, None, None, None) == _lib.SK_ERR_SHAPE
+    assert f(FAKE, FAKE, 4097, 0.1, 0.0, 10, FAKE, None, None, None) == _lib.SK_ERR_SHAPE
+    assert f(FAKE, FAKE, 5, -0.1, 0.0, 10, FAKE, None, None, None) == _lib.SK_ERR_VALUE
+    assert f(FAKE, FAKE, 5, float("nan"), 0.0, 10, FAKE, None, None, None) == _lib.SK_ERR_VALUE
+    assert f(FAKE, FAKE, 5, 0.1, -1.0, 10, FAKE, None, None, None) == _lib.SK_ERR_VALUE
+    assert f(FAKE, FAKE, 5, 0.1, 0.0, -1, FAKE, None, None, None) == _lib.SK_ERR_SHAPE
+    assert g(FAKE, FAKE, 5, 6, 10, 10, 0.0, FAKE, FAKE, None, None) == _lib.SK_ERR_VALUE
+    assert g(FAKE, FAKE, 5, 0, 10, 10, 0.0, FAKE, FAKE, None, None) == _lib.SK_ERR_VALUE
+    assert g(FAKE, FAKE, 5, 2, 10, 0, 0.0, FAKE, FAKE, None, None) == _lib.SK_ERR_VALUE
+    assert g(FAKE, FAKE, 5, 2, 10, 10, 0.0, FAKE, None, None, None) == _lib.SK_ERR_NULL
