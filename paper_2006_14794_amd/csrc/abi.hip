@@ -123,10 +123,17 @@ int64_t choose_run(int64_t nx, int64_t ny, int32_t tuned) {
 // persistent wave slot.
 constexpr int64_t kPairSlots = 4096;
 
+// Pipelined bands (pair_band_kernel) for batches of at most this many pairs
+// whose grids need several bands, within a slot budget.
+constexpr int64_t kPipeMaxPairs = 256;
+constexpr size_t kPipeCapBytes = size_t(1) << 30;
+
 struct PairLayout {
   int rows_lo, rows_hi;
   int64_t slots, band_stride;  // doubles per slot
-  size_t order, counts, bands, total;
+  bool pipe;                   // long class as pipelined band tasks
+  int64_t tasks_max;           // upper bound of the band tasks
+  size_t order, counts, bands, task_base, tbuf, total;
 };
 
 PairLayout pair_layout(const sk_paths* X0, const sk_paths* Y0, int32_t lam0, bool gram) {
@@ -153,13 +160,24 @@ PairLayout pair_layout(const sk_paths* X0, const sk_paths* Y0, int32_t lam0, boo
   L.slots = ((L.slots < 1 ? 1 : L.slots) + 3) & ~int64_t(3);
   const int64_t longer = (X->len > Y->len ? X->len : Y->len);
   L.band_stride = (longer + 2 * sk::kStreamPad) << lam;
+  const int64_t nb_max = L.rows_hi ? (rows + 64 * (int64_t)L.rows_hi - 1) / (64 * L.rows_hi) : 1;
+  L.tasks_max = npairs * nb_max;
+  L.pipe = L.rows_hi > 0 && nb_max > 1 && npairs <= kPipeMaxPairs &&
+           (size_t)L.tasks_max * (size_t)L.band_stride * sizeof(double) <= kPipeCapBytes;
   size_t off = forward_ws(X, Y);
   L.order = off;
   off += align256((size_t)(npairs > 0 ? npairs : 1) * sizeof(int32_t));
   L.counts = off;
-  off += 256;  // counts[2], counters[2]
+  off += 256;  // counts[2], counters[2], the band-task counter
   L.bands = off;
   off += align256((size_t)L.slots * (size_t)L.band_stride * sizeof(double));
+  L.task_base = off;
+  L.tbuf = off;
+  if (L.pipe) {
+    off += align256((size_t)(npairs + 1) * sizeof(int32_t));
+    L.tbuf = off;
+    off += align256((size_t)L.tasks_max * (size_t)L.band_stride * sizeof(double));
+  }
   L.total = off;
   return L;
 }
@@ -359,8 +377,26 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam0, float* o
   a.order = order;
   a.count = counts;
   a.counter = counts + 2;
-  hipError_t e =
-      sk::launch_pairs(a, lam, PL.rows_hi, d, PL.slots, stream, tune.pair_blocks_per_cu);
+  hipError_t e = hipSuccess;
+  if (PL.pipe) {
+    // long class: every band of a pair at once (pipelined band tasks)
+    int32_t* task_base = reinterpret_cast<int32_t*>(base + PL.task_base);
+    double* tbuf = reinterpret_cast<double*>(base + PL.tbuf);
+    if (sk::launch_fill_u64(reinterpret_cast<uint64_t*>(tbuf), PL.tasks_max * PL.band_stride,
+                            sk::kBandSlotSentinel, stream) != hipSuccess)
+      return SK_ERR_HIP;
+    if (sk::launch_band_plan(pp, PL.rows_hi, task_base, counts + 4, stream) != hipSuccess)
+      return SK_ERR_HIP;
+    sk::PairArgs b = a;
+    b.task_base = task_base;
+    b.task_counter = counts + 4;
+    b.tbuf = tbuf;
+    b.tstride = PL.band_stride;
+    e = sk::launch_pair_bands(b, lam, PL.rows_hi, d, (PL.tasks_max + 3) & ~int64_t(3), stream,
+                              tune.pair_blocks_per_cu);
+  } else {
+    e = sk::launch_pairs(a, lam, PL.rows_hi, d, PL.slots, stream, tune.pair_blocks_per_cu);
+  }
   if (e == hipSuccess) {
     // the short class follows the long one in `order`; its offset (the long
     // class's count) is only known on the device, where the kernel reads it

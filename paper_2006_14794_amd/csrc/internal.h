@@ -138,6 +138,11 @@ struct PairArgs {
   float* out;               // out[pid]
   int64_t gram_ny;          // 0: pair pid is (x_pid, y_pid); else (x_{pid / gram_ny}, y_{pid % gram_ny})
   int32_t implicit;         // 1: the implicit scheme's cell factor (2 + h) / (2 - h)
+  // pipelined bands (pair_band_kernel): band tasks of the class in `order`
+  const int32_t* task_base; // device [count + 1]: first task of each pair, total at [count]
+  int32_t* task_counter;    // device queue head over the tasks
+  double* tbuf;             // per task: tstride doubles (its bottom row), sentinel-filled
+  int64_t tstride;
 };
 
 struct PairPlanArgs {
@@ -153,6 +158,18 @@ struct PairPlanArgs {
 };
 
 hipError_t launch_pair_plan(const PairPlanArgs& p, hipStream_t stream);
+// Band tasks of the long class (order[0 .. counts[0])): task_base[k] = sum of
+// the band counts (rows / (64 R), rounded up) of the pairs before k, the total
+// at task_base[counts[0]]; zeroes *task_counter.  counts[0] <= 1024.
+hipError_t launch_band_plan(const PairPlanArgs& p, int rows_per_lane, int32_t* task_base,
+                            int32_t* task_counter, hipStream_t stream);
+// The pipelined band kernel over those tasks (persistent, like launch_pairs).
+hipError_t launch_pair_bands(const PairArgs& a, int lam, int rows_per_lane, int dim,
+                             int64_t max_waves, hipStream_t stream, int blocks_per_cu = 0);
+// p[0 .. n) = v (64-bit pattern), as a kernel
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t stream);
+// The sentinel of the pipelined bands' slots (a signalling NaN arithmetic never yields).
+constexpr uint64_t kBandSlotSentinel = 0x7FF40000DEAD5EB0ull;
 // Persistent launch: min(max_waves, blocks_per_cu 4-wave workgroups per CU)
 // wavefronts; blocks_per_cu 0 takes the occupancy limit.  Waves never wait on
 // one another, so any count is correct; it only changes the balance.
@@ -223,7 +240,7 @@ hipError_t launch_gram_mfma(const GramArgs& a, int precision, hipStream_t stream
 // Compiled sweep kernels by kind, dyadic order, rows per lane and channels
 // (nullptr when the configuration is not compiled).
 enum { kKernelForward = 0, kKernelForwardStore = 1, kKernelAdjoint = 2, kKernelPair = 3,
-       kKernelLifted = 4, kKernelForwardImplicit = 5 };
+       kKernelLifted = 4, kKernelForwardImplicit = 5, kKernelPairBand = 6 };
 void* sweep_fn(int kind, int lam, int rows_per_lane, int dim);
 
 }  // namespace sk

@@ -174,5 +174,221 @@ __global__ __launch_bounds__(256) void pair_kernel(const PairArgs a) {
   }
 }
 
+// Pipelined row bands for a few long pairs.  The queue holds band tasks in
+// pair order, band by band (task_base[k] = first task of the k-th pair of the
+// class); a wave takes one task, i.e. one band of one pair, so all bands of a
+// pair are swept at the same time, each one lagging the band above by a
+// little over one wave's pipeline fill.
+//   * Band b writes its bottom row (one double per fine column) into the
+//     task's own slot buffer with agent-scope atomic stores, once per value.
+//   * The slot buffers are filled with a signalling-NaN sentinel beforehand
+//     (arithmetic never produces it), so a value is ready when it differs from
+//     the sentinel: band b+1 polls the slots of task tau - 1 with agent-scope
+//     atomic loads, kChunk coarse columns at a time, one chunk ahead, staging
+//     them in LDS for lane 0.
+//   * A task only waits on the task taken just before it (same pair), whose
+//     wave is running, so the chain always advances; the wait is bounded all
+//     the same, and on expiry the missing values become NaN, which flows to
+//     the pair's output and releases the bands below.
+constexpr int kChunk = 16;         // coarse columns staged per chunk
+constexpr int kSpinMax = 1 << 18;  // polls per value before giving up
+
+__device__ __forceinline__ bool is_sentinel(double v) {
+  return (uint64_t)__double_as_longlong(v) == kBandSlotSentinel;
+}
+
+template <int R, int LAM, int D>
+__global__ __launch_bounds__(256) void pair_band_kernel(const PairArgs a) {
+  constexpr int DP = (D + 3) & ~3;
+  constexpr int S = 1 << LAM;
+  constexpr int CR = (R >> LAM) > 0 ? (R >> LAM) : 1;
+  constexpr int CHS = kChunk * S;        // doubles per chunk
+  constexpr int PER = (CHS + 63) / 64;   // doubles per lane per chunk
+  __shared__ double stage[4][2][CHS];
+
+  const int lane = threadIdx.x & 63;
+  const int wl = threadIdx.x >> 6;
+  const int32_t count = *a.count;
+  const int32_t* __restrict__ order = a.order;
+  const int32_t total_tasks = a.task_base[count];
+
+  for (;;) {
+    int32_t tau = 0;
+    if (lane == 0) tau = atomicAdd(a.task_counter, 1);
+    tau = __shfl(tau, 0, 64);
+    if (tau >= total_tasks) break;
+    // the pair of this task: the last k with task_base[k] <= tau
+    int32_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (a.task_base[mid] <= tau) lo = mid; else hi = mid - 1;
+    }
+    const int32_t band = tau - a.task_base[lo];
+    const int32_t pid = order[lo];
+    const int64_t ix = a.gram_ny ? pid / a.gram_ny : pid;
+    const int64_t iy = a.gram_ny ? pid - ix * a.gram_ny : pid;
+    const int32_t mx = n_inc(a.x_n, a.x_len, ix), my = n_inc(a.y_n, a.y_len, iy);
+    if (mx <= 0 || my <= 0) {  // one task for such a pair
+      if (lane == 0) a.out[pid] = (mx < 0 || my < 0) ? __builtin_nanf("") : 1.0f;
+      continue;
+    }
+    const bool swap = mx > my;
+    const int32_t m = swap ? my : mx, n = swap ? mx : my;
+    const float* __restrict__ rinc =
+        swap ? a.incy + first_row(a.y_start, a.y_len, iy) * DP
+             : a.incx + first_row(a.x_start, a.x_len, ix) * DP;
+    const float* __restrict__ cinc =
+        swap ? a.incx + first_row(a.x_start, a.x_len, ix) * DP
+             : a.incy + first_row(a.y_start, a.y_len, iy) * DP;
+    const int M = m << LAM;
+    const int nb = (M + 64 * R - 1) / (64 * R);
+    const int off = nb * 64 * R - M;
+    const int32_t nsteps = (int32_t)sweep_steps(n);
+    const bool top = (band == 0), last = (band == nb - 1);
+    double* __restrict__ own = a.tbuf + (int64_t)tau * a.tstride;
+    const double* __restrict__ above = a.tbuf + (int64_t)(tau - 1) * a.tstride;
+
+    const int row0 = (band * 64 + lane) * R - off;
+    const int p0 = row0 >> LAM;
+    float dx[CR][D];
+#pragma unroll
+    for (int c = 0; c < CR; ++c) {
+      float t[DP];
+      if (p0 + c >= 0 && p0 + c < m) {
+        load_row<DP>(rinc + (int64_t)(p0 + c) * DP, t);
+      } else {
+#pragma unroll
+        for (int q = 0; q < DP; ++q) t[q] = 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < D; ++q) dx[c][q] = t[q];
+    }
+
+    // upper neighbours of lane 0, staged chunk by chunk from the band above
+    bool failed = false;  // wave-uniform
+    double pf[PER];
+    auto fetch = [&](int32_t chunk) {  // issue the loads of a chunk
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = lane + 64 * i;
+        const int32_t col = chunk * kChunk + e / S;
+        pf[i] = 0.0;
+        if (!top && e < CHS && col < n)
+          pf[i] = __hip_atomic_load(above + (int64_t)col * S + (e % S), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+      }
+    };
+    auto commit = [&](int32_t chunk) {  // wait for a chunk's values, then stage them
+      bool missing = false;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = lane + 64 * i;
+        const int32_t col = chunk * kChunk + e / S;
+        double v = pf[i];
+        if (!top && e < CHS && col < n) {
+          int spins = 0;
+          while (!failed && is_sentinel(v) && spins < kSpinMax) {
+            ++spins;
+            __builtin_amdgcn_s_sleep(2);
+            v = __hip_atomic_load(above + (int64_t)col * S + (e % S), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+          }
+          if (is_sentinel(v)) {
+            v = __builtin_nan("");
+            missing = true;
+          }
+        }
+        if (e < CHS) stage[wl][chunk & 1][e] = top ? 1.0 : v;
+      }
+      // a value that never came poisons the rest of this band (no more waits)
+      failed = failed || __ballot(missing) != 0;
+    };
+
+    double u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = 1.0;
+    double pub[S];
+#pragma unroll
+    for (int cc = 0; cc < S; ++cc) pub[cc] = 1.0;
+    double up_last = 1.0;
+    int32_t g = -lane;
+    const float* __restrict__ yp = cinc + (int64_t)g * DP;
+    auto bnd_load = [&](int32_t t, double (&v)[S]) {
+#pragma unroll
+      for (int cc = 0; cc < S; ++cc) v[cc] = stage[wl][(t / kChunk) & 1][(t % kChunk) * S + cc];
+    };
+
+    fetch(0);
+    commit(0);
+    fetch(1);
+    float dyA[DP], dyB[DP], dyC[DP];
+    double bA[S], bB[S], bC[S];
+    load_row<DP>(yp, dyA);
+    load_row<DP>(yp + DP, dyB);
+    bnd_load(0, bA);
+    bnd_load(1, bB);
+    double result = 1.0;
+
+    auto step = [&](int32_t t, float (&dy)[DP], float (&refill)[DP], double (&bv)[S],
+                    double (&brefill)[S]) {
+      load_row<DP>(yp + 2 * DP, refill);
+      if ((t + 2) % kChunk == 0) {  // the next chunk is read from step t on
+        const int32_t c = (t + 2) / kChunk;
+        commit(c);
+        fetch(c + 1);
+      }
+      bnd_load(t + 2, brefill);
+      float h32[CR];
+#pragma unroll
+      for (int c = 0; c < CR; ++c) {
+        float s = 0.0f;
+#pragma unroll
+        for (int q = 0; q < D; ++q) s = __builtin_fmaf(dx[c][q], dy[q], s);
+        h32[c] = s;
+      }
+      double up[S];
+#pragma unroll
+      for (int cc = 0; cc < S; ++cc) up[cc] = from_prev_lane(pub[cc], bv[cc]);
+
+      if ((uint32_t)g < (uint32_t)n) {
+        double gk[CR];
+#pragma unroll
+        for (int c = 0; c < CR; ++c) {
+          const double h = (double)h32[c] * a.scale;  // exact: scale is a power of two
+          gk[c] = a.implicit ? fwd::implicit_factor(h)
+                             : __builtin_fma((double)h32[c], a.scale, 1.0);
+        }
+        double v[R][S];
+        float sv[1];
+        fwd::cell_block<R, LAM, CR, false>(v, sv, u, up, up_last, gk);
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[r][S - 1];
+#pragma unroll
+        for (int cc = 0; cc < S; ++cc) pub[cc] = v[R - 1][cc];
+        up_last = up[S - 1];
+        if (lane == 63) {
+          if (!last) {
+#pragma unroll
+            for (int cc = 0; cc < S; ++cc)
+              __hip_atomic_store(own + (int64_t)g * S + cc, pub[cc], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+          } else if (g == n - 1) {
+            result = u[R - 1];
+          }
+        }
+      }
+      ++g;
+      yp += DP;
+    };
+
+    for (int32_t t = 0; t < nsteps; t += 3) {
+      step(t, dyA, dyC, bA, bC);
+      step(t + 1, dyB, dyA, bB, bA);
+      step(t + 2, dyC, dyB, bC, bB);
+    }
+    if (last && lane == 63) a.out[pid] = (float)result;
+  }
+}
+
 }  // namespace pairk
 }  // namespace sk

@@ -104,7 +104,52 @@ __global__ __launch_bounds__(1024) void pair_plan_kernel(
   }
 }
 
+// One workgroup: band counts of the long-class pairs (order[0 .. counts[0]))
+// and their exclusive prefix sum.
+__global__ __launch_bounds__(1024) void band_plan_kernel(
+    const int32_t* __restrict__ x_n, int32_t x_len, const int32_t* __restrict__ y_n,
+    int32_t y_len, int32_t lam, int32_t rows, int64_t gram_ny,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ counts,
+    int32_t* __restrict__ task_base, int32_t* __restrict__ task_counter) {
+  __shared__ int32_t scan[1024];
+  const int32_t count = counts[0];
+  const int32_t k = threadIdx.x;
+  int32_t nb = 0;
+  if (k < count) {
+    const int32_t pid = order[k];
+    const int64_t ix = gram_ny ? pid / gram_ny : pid, iy = gram_ny ? pid - ix * gram_ny : pid;
+    const int32_t mx = incs(x_n, x_len, ix), my = incs(y_n, y_len, iy);
+    if (mx <= 0 || my <= 0) {
+      nb = 1;  // one task writes its value
+    } else {
+      const int64_t M = (int64_t)(mx < my ? mx : my) << lam;
+      nb = (int32_t)((M + 64 * (int64_t)rows - 1) / (64 * (int64_t)rows));
+    }
+  }
+  scan[k] = nb;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan
+    const int32_t v = k >= o ? scan[k - o] : 0;
+    __syncthreads();
+    scan[k] += v;
+    __syncthreads();
+  }
+  if (k < count) task_base[k] = scan[k] - nb;
+  if (k == 1023) {
+    task_base[count] = scan[1023];
+    *task_counter = 0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_band_plan(const PairPlanArgs& p, int rows_per_lane, int32_t* task_base,
+                            int32_t* task_counter, hipStream_t stream) {
+  hipLaunchKernelGGL(band_plan_kernel, dim3(1), dim3(1024), 0, stream, p.x_n, p.x_len, p.y_n,
+                     p.y_len, p.lam, rows_per_lane, p.gram_ny, p.order, p.counts, task_base,
+                     task_counter);
+  return hipGetLastError();
+}
 
 hipError_t launch_pair_plan(const PairPlanArgs& p, hipStream_t stream) {
   hipLaunchKernelGGL(pair_plan_kernel, dim3(1), dim3(1024), 0, stream, p.x_n, p.x_len, p.y_n,
@@ -113,9 +158,10 @@ hipError_t launch_pair_plan(const PairPlanArgs& p, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_pairs(const PairArgs& a, int lam, int R, int d, int64_t max_waves,
-                        hipStream_t stream, int blocks_per_cu_wanted) {
-  auto f = reinterpret_cast<void (*)(const PairArgs)>(sweep_fn(kKernelPair, lam, R, d));
+namespace {
+hipError_t launch_persistent(int kind, const PairArgs& a, int lam, int R, int d,
+                             int64_t max_waves, hipStream_t stream, int blocks_per_cu_wanted) {
+  auto f = reinterpret_cast<void (*)(const PairArgs)>(sweep_fn(kind, lam, R, d));
   if (!f) return hipErrorInvalidValue;
   int dev = 0, cus = 0, blocks_per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
@@ -130,6 +176,18 @@ hipError_t launch_pairs(const PairArgs& a, int lam, int R, int d, int64_t max_wa
   const int64_t blocks = waves / 4 > 0 ? waves / 4 : 1;
   hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, stream, a);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_pairs(const PairArgs& a, int lam, int R, int d, int64_t max_waves,
+                        hipStream_t stream, int blocks_per_cu_wanted) {
+  return launch_persistent(kKernelPair, a, lam, R, d, max_waves, stream, blocks_per_cu_wanted);
+}
+
+hipError_t launch_pair_bands(const PairArgs& a, int lam, int R, int d, int64_t max_waves,
+                             hipStream_t stream, int blocks_per_cu_wanted) {
+  return launch_persistent(kKernelPairBand, a, lam, R, d, max_waves, stream,
+                           blocks_per_cu_wanted);
 }
 
 }  // namespace sk

@@ -1,10 +1,10 @@
 // Instantiations of one sweep kernel (SK_KIND: forward, forward with store,
-// adjoint, persistent pairs, lifted forward, implicit forward) at one dyadic order SK_LAM.  Included by sweep_k{kind}_l{lam}.hip
+// adjoint, persistent pairs, lifted forward, implicit forward, pipelined bands) at one dyadic order SK_LAM.  Included by sweep_k{kind}_l{lam}.hip
 // so that the configurations compile in parallel translation units.
 #include "dispatch.h"
 #if SK_KIND == 2
 #include "sweep_bwd_kernel.h"
-#elif SK_KIND == 3
+#elif SK_KIND == 3 || SK_KIND == 6
 #include "pair_kernel.h"
 #elif SK_KIND == 4
 #include "lifted_kernel.h"
@@ -47,6 +47,17 @@ struct Pair {
   static Fn get() {
     if constexpr (sweep_fits(R, LAM, D))
       return reinterpret_cast<void*>(&pairk::pair_kernel<R, LAM, D>);
+    else
+      return nullptr;
+  }
+};
+#elif SK_KIND == 6
+struct PairBand {
+  using Fn = void*;
+  template <int R, int LAM, int D>
+  static Fn get() {
+    if constexpr (sweep_fits(R, LAM, D))
+      return reinterpret_cast<void*>(&pairk::pair_band_kernel<R, LAM, D>);
     else
       return nullptr;
   }
@@ -111,6 +122,8 @@ void* SK_CAT(SK_CAT(sweep_fn_k3_l, SK_LAM), _)(int R, int d) { return pick_fixed
 void* SK_CAT(SK_CAT(sweep_fn_k4_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Lifted>(R, d); }
 #elif SK_KIND == 5
 void* SK_CAT(SK_CAT(sweep_fn_k5_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<FwdImplicit>(R, d); }
+#elif SK_KIND == 6
+void* SK_CAT(SK_CAT(sweep_fn_k6_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<PairBand>(R, d); }
 #else
 void* SK_CAT(SK_CAT(sweep_fn_k2_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Adjoint>(R, d); }
 #endif
