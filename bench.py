@@ -245,7 +245,7 @@ def bench_ragged(args):
         "bf16_increments_ms_per_step": wall16 * 1e3 / args.steps,
         "roofline": {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": VALU_PEAK_TOPS,
                      "unit": "Tops/s", "frac": ops / avg_s / 1e12 / VALU_PEAK_TOPS,
-                     "traffic": None, "kernel": "pair_kernel (events around the timed calls)",
+                     "traffic": None, "kernel": "pair_band_kernel (events around the timed calls)",
                      "ops_per_cell": sweep_ops_per_cell(d, lam)},
     }
     if not args.no_cpu_baseline:

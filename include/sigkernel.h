@@ -288,7 +288,7 @@ size_t sigkernel_workspace_bytes(int32_t op, const sk_paths *X, const sk_paths *
 /*
  * Launch tuning (batching of pairs onto waves; no effect on any result).
  *
- * The Gram and pair calls map pairs onto one-wave sweeps.  Three launch
+ * The Gram and pair calls map pairs onto one-wave sweeps.  Four launch
  * parameters change only how that work is spread over the chip, never the
  * arithmetic of a pair, so the forward outputs are bit-identical under every
  * tuning (a Gram backward sums its per-pair gradients in an order that
@@ -298,7 +298,12 @@ size_t sigkernel_workspace_bytes(int32_t op, const sk_paths *X, const sk_paths *
  *    without draining the wavefront);
  *  - waves_per_block: one-wave sweeps per workgroup (1, 2 or 4);
  *  - pair_blocks_per_cu: resident 4-wave workgroups per CU of the persistent
- *    pair kernel (independent pairs, ragged batches, tall paths).
+ *    pair kernel (independent pairs, ragged batches, tall paths);
+ *  - pair_bands: how the persistent pair kernel sweeps a grid taller than one
+ *    wave's rows: 0 (built-in) as pipelined band tasks, one wave per band, all
+ *    bands of a pair at once, when their hand-over slots fit a 1 GiB budget
+ *    (else as 1); 1 with one wave per pair, band after band.  The workspace
+ *    size does not depend on it.
  * A value of 0 keeps the built-in rule.  The library holds a table from
  * problem keys to tunings; calls whose key is in the table use its entry.
  * The workspace size of a Gram backward depends on `run`: query
@@ -321,7 +326,7 @@ typedef struct sk_tune {
     int32_t run;                 /* 1 .. 1024, 0 = built-in rule                       */
     int32_t waves_per_block;     /* 1, 2 or 4, 0 = 4                                   */
     int32_t pair_blocks_per_cu;  /* 1 .. 64, 0 = occupancy limit                       */
-    int32_t reserved;            /* 0                                                  */
+    int32_t pair_bands;          /* 0 = built-in rule (pipelined), 1 = sequential      */
 } sk_tune;
 
 /* The key of a call (op, batches, order and flags as the call receives them). */

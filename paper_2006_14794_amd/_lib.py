@@ -119,7 +119,7 @@ class SkTune(ctypes.Structure):
         ("run", ctypes.c_int32),
         ("waves_per_block", ctypes.c_int32),
         ("pair_blocks_per_cu", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("pair_bands", ctypes.c_int32),
     ]
 
 

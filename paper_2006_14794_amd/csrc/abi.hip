@@ -123,9 +123,8 @@ int64_t choose_run(int64_t nx, int64_t ny, int32_t tuned) {
 // persistent wave slot.
 constexpr int64_t kPairSlots = 4096;
 
-// Pipelined bands (pair_band_kernel) for batches of at most this many pairs
-// whose grids need several bands, within a slot budget.
-constexpr int64_t kPipeMaxPairs = 256;
+// Pipelined bands (pair_band_kernel) for batches whose grids need several
+// bands, when every band task's slot buffer fits this budget.
 constexpr size_t kPipeCapBytes = size_t(1) << 30;
 
 struct PairLayout {
@@ -162,7 +161,7 @@ PairLayout pair_layout(const sk_paths* X0, const sk_paths* Y0, int32_t lam0, boo
   L.band_stride = (longer + 2 * sk::kStreamPad) << lam;
   const int64_t nb_max = L.rows_hi ? (rows + 64 * (int64_t)L.rows_hi - 1) / (64 * L.rows_hi) : 1;
   L.tasks_max = npairs * nb_max;
-  L.pipe = L.rows_hi > 0 && nb_max > 1 && npairs <= kPipeMaxPairs &&
+  L.pipe = L.rows_hi > 0 && nb_max > 1 && npairs <= INT32_MAX &&
            (size_t)L.tasks_max * (size_t)L.band_stride * sizeof(double) <= kPipeCapBytes;
   size_t off = forward_ws(X, Y);
   L.order = off;
@@ -351,7 +350,11 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam0, float* o
   pp.npairs = (int32_t)npairs;
   pp.gram_ny = gram ? Y->n_paths : 0;
   pp.lam = lam;
-  pp.rows_lo = PL.rows_lo;
+  // pipelined bands: every pair with cells joins the band-task queue (a short
+  // pair is one task at the end of it), so the short class keeps only the
+  // pairs without cells
+  const bool pipe = PL.pipe && tune.pair_bands != 1;
+  pp.rows_lo = pipe ? 0 : PL.rows_lo;
   pp.rows_hi = PL.rows_hi;
   pp.order = order;
   pp.counts = counts;
@@ -378,14 +381,15 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam0, float* o
   a.count = counts;
   a.counter = counts + 2;
   hipError_t e = hipSuccess;
-  if (PL.pipe) {
+  if (pipe) {
     // long class: every band of a pair at once (pipelined band tasks)
     int32_t* task_base = reinterpret_cast<int32_t*>(base + PL.task_base);
     double* tbuf = reinterpret_cast<double*>(base + PL.tbuf);
-    if (sk::launch_fill_u64(reinterpret_cast<uint64_t*>(tbuf), PL.tasks_max * PL.band_stride,
-                            sk::kBandSlotSentinel, stream) != hipSuccess)
-      return SK_ERR_HIP;
     if (sk::launch_band_plan(pp, PL.rows_hi, task_base, counts + 4, stream) != hipSuccess)
+      return SK_ERR_HIP;
+    if (sk::launch_fill_task_slots(reinterpret_cast<uint64_t*>(tbuf), task_base, counts,
+                                   PL.band_stride, PL.tasks_max * PL.band_stride,
+                                   sk::kBandSlotSentinel, stream) != hipSuccess)
       return SK_ERR_HIP;
     sk::PairArgs b = a;
     b.task_base = task_base;

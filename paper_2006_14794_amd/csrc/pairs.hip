@@ -113,32 +113,50 @@ __global__ __launch_bounds__(1024) void band_plan_kernel(
     int32_t* __restrict__ task_base, int32_t* __restrict__ task_counter) {
   __shared__ int32_t scan[1024];
   const int32_t count = counts[0];
-  const int32_t k = threadIdx.x;
-  int32_t nb = 0;
-  if (k < count) {
-    const int32_t pid = order[k];
-    const int64_t ix = gram_ny ? pid / gram_ny : pid, iy = gram_ny ? pid - ix * gram_ny : pid;
-    const int32_t mx = incs(x_n, x_len, ix), my = incs(y_n, y_len, iy);
-    if (mx <= 0 || my <= 0) {
-      nb = 1;  // one task writes its value
-    } else {
-      const int64_t M = (int64_t)(mx < my ? mx : my) << lam;
-      nb = (int32_t)((M + 64 * (int64_t)rows - 1) / (64 * (int64_t)rows));
+  // 1024 pairs at a time, carrying the running total between chunks
+  int32_t carry = 0;
+  for (int32_t base = 0; base < count; base += 1024) {
+    const int32_t k = base + (int32_t)threadIdx.x;
+    int32_t nb = 0;
+    if (k < count) {
+      const int32_t pid = order[k];
+      const int64_t ix = gram_ny ? pid / gram_ny : pid, iy = gram_ny ? pid - ix * gram_ny : pid;
+      const int32_t mx = incs(x_n, x_len, ix), my = incs(y_n, y_len, iy);
+      if (mx <= 0 || my <= 0) {
+        nb = 1;  // one task writes its value
+      } else {
+        const int64_t M = (int64_t)(mx < my ? mx : my) << lam;
+        nb = (int32_t)((M + 64 * (int64_t)rows - 1) / (64 * (int64_t)rows));
+      }
     }
-  }
-  scan[k] = nb;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan
-    const int32_t v = k >= o ? scan[k - o] : 0;
+    scan[threadIdx.x] = nb;
     __syncthreads();
-    scan[k] += v;
-    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan
+      const int32_t v = (int)threadIdx.x >= o ? scan[threadIdx.x - o] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (k < count) task_base[k] = carry + scan[threadIdx.x] - nb;
+    carry += scan[1023];
+    __syncthreads();  // scan[] is rewritten by the next chunk
   }
-  if (k < count) task_base[k] = scan[k] - nb;
-  if (k == 1023) {
-    task_base[count] = scan[1023];
+  if (threadIdx.x == 0) {
+    task_base[count] = carry;
     *task_counter = 0;
   }
+}
+
+// The sentinel in the slot buffers of the tasks the band plan numbered
+// (task_base[count] of them, at most n_max / stride).
+__global__ __launch_bounds__(256) void fill_task_slots_kernel(
+    uint64_t* __restrict__ tbuf, const int32_t* __restrict__ task_base,
+    const int32_t* __restrict__ counts, int64_t stride, int64_t n_max, uint64_t v) {
+  int64_t n = (int64_t)task_base[counts[0]] * stride;
+  if (n > n_max) n = n_max;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    tbuf[i] = v;
 }
 
 }  // namespace
@@ -148,6 +166,17 @@ hipError_t launch_band_plan(const PairPlanArgs& p, int rows_per_lane, int32_t* t
   hipLaunchKernelGGL(band_plan_kernel, dim3(1), dim3(1024), 0, stream, p.x_n, p.x_len, p.y_n,
                      p.y_len, p.lam, rows_per_lane, p.gram_ny, p.order, p.counts, task_base,
                      task_counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_task_slots(uint64_t* tbuf, const int32_t* task_base,
+                                  const int32_t* counts, int64_t stride, int64_t n_max,
+                                  uint64_t v, hipStream_t stream) {
+  if (n_max <= 0) return hipSuccess;
+  int64_t blocks = (n_max + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(fill_task_slots_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, tbuf,
+                     task_base, counts, stride, n_max, v);
   return hipGetLastError();
 }
 

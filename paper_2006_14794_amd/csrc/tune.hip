@@ -30,7 +30,8 @@ bool valid_tune(const sk_tune& t) {
   return t.run >= 0 && t.run <= 1024 &&
          (t.waves_per_block == 0 || t.waves_per_block == 1 || t.waves_per_block == 2 ||
           t.waves_per_block == 4) &&
-         t.pair_blocks_per_cu >= 0 && t.pair_blocks_per_cu <= 64 && t.reserved == 0;
+         t.pair_blocks_per_cu >= 0 && t.pair_blocks_per_cu <= 64 && t.pair_bands >= 0 &&
+         t.pair_bands <= 1;
 }
 
 // The forward call an autotuning candidate is timed on.
@@ -50,6 +51,7 @@ std::vector<sk_tune> candidates(int32_t op, const sk_paths* X, const sk_paths* Y
                          sk::choose_rows_per_lane(fine_rows, lam > 3 ? 3 : lam, X->dim) == 0;
   if (pair_path) {
     for (int b : {0, 1, 2, 3, 4, 6, 8}) c.push_back(sk_tune{0, 0, b, 0});
+    for (int b : {0, 2, 4}) c.push_back(sk_tune{0, 0, b, 1});  // sequential bands
     return c;
   }
   std::vector<int> runs;

@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import SkTune, SkTuneKey
 
 KEY_FIELDS = ("op", "dyadic_order", "symmetric", "ragged", "nx", "ny", "x_len", "y_len", "dim")
-TUNE_FIELDS = ("run", "waves_per_block", "pair_blocks_per_cu")
+TUNE_FIELDS = ("run", "waves_per_block", "pair_blocks_per_cu", "pair_bands")
 
 OPS = {"pair": _lib.SK_OP_PAIR, "gram": _lib.SK_OP_GRAM,
        "gram_backward": _lib.SK_OP_GRAM_BACKWARD}
@@ -36,7 +36,6 @@ def _tune_struct(tune: Dict[str, int]) -> SkTune:
     t = SkTune()
     for f in TUNE_FIELDS:
         setattr(t, f, int(tune.get(f, 0)))
-    t.reserved = 0
     return t
 
 

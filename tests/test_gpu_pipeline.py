@@ -1,10 +1,9 @@
-"""Pipelined row bands (pair_band_kernel): a few pairs whose grids need
-several row bands are swept with every band of a pair at once, each band
-handing its bottom row to the next through sentinel-filled slots.  Checked
-against the FP64 oracle, and bitwise against the sequential bands (the same
-pairs inside a batch too large for the pipeline, where each pair's bands run
-one after another in one wave): the hand-over moves the same doubles, so the
-values must be identical."""
+"""Pipelined row bands (pair_band_kernel): pairs whose grids need several
+row bands are swept with every band of a pair at once, each band handing its
+bottom row to the next through sentinel-filled slots.  Checked against the
+FP64 oracle, and bitwise against the sequential bands (the tuning entry
+pair_bands = 1, where each pair's bands run one after another in one wave):
+the hand-over moves the same doubles, so the values must be identical."""
 import numpy as np
 import pytest
 import torch
@@ -38,12 +37,16 @@ def mixed_err(got, ref):
 
 
 def sequential(X, Y, lam, **kw):
-    """The same pairs swept with sequential bands: padded with 300 copies of
-    the last pair, beyond the pipeline's batch limit."""
-    n = X.shape[0]
-    Xb = np.concatenate([X, np.repeat(X[-1:], 300, 0)])
-    Yb = np.concatenate([Y, np.repeat(Y[-1:], 300, 0)])
-    return sk.sigkernel_pair(cuda(Xb), cuda(Yb), lam, **kw).cpu().numpy()[:n]
+    """The same call with each pair's bands swept one after another in one
+    wave (a tuning entry for the call's key, removed afterwards)."""
+    Xt = X if isinstance(X, RaggedPaths) else cuda(X)
+    Yt = Y if isinstance(Y, RaggedPaths) else cuda(Y)
+    key = sk.tune_key("pair", Xt, Yt, lam)
+    sk.tune_set(key, dict(pair_bands=1))
+    try:
+        return sk.sigkernel_pair(Xt, Yt, lam, **kw).cpu().numpy()
+    finally:
+        sk.tune_set(key, None)
 
 
 @pytest.mark.parametrize("lam,L,d", [(3, 300, 2), (1, 1200, 3), (4, 1000, 2), (0, 2600, 2)])
@@ -73,6 +76,37 @@ def test_ragged_mix_of_long_short_and_degenerate():
     ref = oracle.pairs([f64(a) for a in xs], [f64(b) for b in ys], 2)
     assert mixed_err(got, ref).max() <= TOL
     assert got[2] == 1.0 and got[5] == 1.0
+    assert np.array_equal(got, sequential(X, Y, 2))
+
+
+def test_more_pairs_than_one_scan_chunk():
+    """1500 uniform pairs of two bands each: the band plan numbers the tasks
+    over two 1024-pair chunks of its scan."""
+    X = workloads.random_paths(570, 1500, 300, 2)
+    Y = workloads.random_paths(571, 1500, 310, 2)
+    got = sk.sigkernel_pair(cuda(X), cuda(Y), 3).cpu().numpy()
+    idx = np.random.default_rng(572).choice(1500, 24, replace=False)
+    ref = oracle.pairs(f64(X[idx]), f64(Y[idx]), 3)
+    assert mixed_err(got[idx], ref).max() <= TOL
+    assert np.array_equal(got, sequential(X, Y, 3))
+
+
+def test_ragged_batch_across_scan_chunks():
+    """1300 ragged pairs of one to three bands, short pairs and one-point
+    paths among them."""
+    rng = np.random.default_rng(580)
+    lx = rng.integers(60, 700, 1300)
+    ly = rng.integers(60, 700, 1300)
+    lx[::97] = 1
+    xs = [workloads.random_paths(581 + i, 1, int(L), 2)[0] for i, L in enumerate(lx)]
+    ys = [workloads.random_paths(5000 + i, 1, int(L), 2)[0] for i, L in enumerate(ly)]
+    X, Y = RaggedPaths.from_list(xs, "cuda"), RaggedPaths.from_list(ys, "cuda")
+    got = sk.sigkernel_pair(X, Y, 3).cpu().numpy()
+    idx = np.concatenate([np.arange(0, 1300, 97), rng.choice(1300, 16, replace=False)])
+    ref = oracle.pairs([f64(xs[i]) for i in idx], [f64(ys[i]) for i in idx], 3)
+    assert mixed_err(got[idx], ref).max() <= TOL
+    assert np.all(got[::97] == 1.0)
+    assert np.array_equal(got, sequential(X, Y, 3))
 
 
 def test_tall_gram():

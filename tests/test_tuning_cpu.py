@@ -46,9 +46,11 @@ def test_set_get_replace_remove_list():
     kb = key_of(_lib.SK_OP_PAIR, X, X)
     assert tuning.tune_get(ka) is None
     tuning.tune_set(ka, dict(run=8, waves_per_block=2))
-    tuning.tune_set(kb, dict(pair_blocks_per_cu=3))
-    assert tuning.tune_get(ka) == dict(run=8, waves_per_block=2, pair_blocks_per_cu=0)
-    assert tuning.tune_get(kb) == dict(run=0, waves_per_block=0, pair_blocks_per_cu=3)
+    tuning.tune_set(kb, dict(pair_blocks_per_cu=3, pair_bands=1))
+    assert tuning.tune_get(ka) == dict(run=8, waves_per_block=2, pair_blocks_per_cu=0,
+                                       pair_bands=0)
+    assert tuning.tune_get(kb) == dict(run=0, waves_per_block=0, pair_blocks_per_cu=3,
+                                       pair_bands=1)
     tuning.tune_set(ka, dict(run=1, waves_per_block=4))
     assert tuning.tune_get(ka)["run"] == 1
     assert len(tuning.tune_list()) == 2
@@ -59,7 +61,8 @@ def test_set_get_replace_remove_list():
 
 @pytest.mark.parametrize("bad", [dict(run=-1), dict(run=1025), dict(waves_per_block=3),
                                  dict(waves_per_block=8), dict(pair_blocks_per_cu=65),
-                                 dict(pair_blocks_per_cu=-2)])
+                                 dict(pair_blocks_per_cu=-2), dict(pair_bands=2),
+                                 dict(pair_bands=-1)])
 def test_out_of_range_tunings_are_rejected(bad):
     X = SkPaths(FAKE, None, 16, 32, 4)
     k = key_of(_lib.SK_OP_GRAM, X, X)
@@ -68,7 +71,7 @@ def test_out_of_range_tunings_are_rejected(bad):
     assert e.value.status == _lib.SK_ERR_FLAGS
     assert tuning.tune_get(k) is None
     t = SkTune()
-    t.reserved = 1
+    t.pair_bands = 7
     assert _lib.load().sigkernel_tune_set(ctypes.byref(tuning._key_struct(k)),
                                           ctypes.byref(t)) == _lib.SK_ERR_FLAGS
 
