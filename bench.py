@@ -28,8 +28,9 @@ sys.path.insert(0, ROOT)
 METRIC = "Goursat grid-cell updates/s (Gram batch) and pairs/s at stated rel err vs FP64"
 
 # MI355X FP64 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz double operations
-# per second (78.6 TFLOP/s counting an FMA as two); non-packed float32
-# add/FMA issue at twice this rate.
+# per second (78.6 TFLOP/s counting an FMA as two).  The published float32
+# peak is twice this (packed float32 instructions, which these kernels do not
+# use).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
@@ -70,8 +71,8 @@ def parse():
 def sweep_ops_per_cell(d: int, lam: int) -> float:
     """VALU work per fine cell in FP64-operation equivalents: the cell update
     (one double add and one double FMA) plus the coarse inner product (d float
-    FMAs per coarse cell, shared by 4^lam fine cells; a float FMA issues at
-    twice the double rate, so it counts 1/2)."""
+    FMAs per coarse cell, shared by 4^lam fine cells; a float FMA counts 1/2,
+    after the published float32 peak, which is twice the double one)."""
     return 2.0 + 0.5 * d / float(4 ** lam)
 
 

@@ -71,12 +71,16 @@ __global__ __launch_bounds__(256) void increments_kernel(
     dstart = k * (int64_t)n * rep;
   }
   // increment p fills rows p rep .. p rep + rep - 1 (refinement beyond the
-  // sweep's compiled orders: rep equal sub-increments of a straight segment)
-  const int64_t total = (int64_t)n * rep * dpad;
-  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
-    const int64_t row = e / dpad;
-    const int64_t p = row / rep;
-    const int c = (int)(e - row * dpad);
+  // sweep's compiled orders: rep equal sub-increments of a straight segment).
+  // Element (row, c) of the block's rows, stepped by the block size without
+  // divisions; rep is a power of two.
+  const int64_t nrows = (int64_t)n * rep;
+  const int rs = __builtin_ctz((unsigned)rep);
+  const int32_t drow = (int32_t)blockDim.x / dpad, dc = (int32_t)blockDim.x - drow * dpad;
+  int64_t row = (int32_t)threadIdx.x / dpad;
+  int32_t c = (int32_t)threadIdx.x - (int32_t)row * dpad;
+  while (row < nrows) {
+    const int64_t p = row >> rs;
     float v = 0.0f;
     if (c < d) {
       const float a = pts[(pstart + p + 1) * d + c];
@@ -89,6 +93,12 @@ __global__ __launch_bounds__(256) void increments_kernel(
       v *= scale;  // power-of-two scale (including 1 / rep): exact
     }
     incr[(dstart + row) * dpad + c] = v;
+    row += drow;
+    c += dc;
+    if (c >= dpad) {
+      c -= dpad;
+      ++row;
+    }
   }
 }
 
@@ -123,11 +133,18 @@ __global__ __launch_bounds__(256) void nodes_kernel(
     pstart = k * (int64_t)len;
     dstart = k * (int64_t)len;
   }
-  const int64_t total = (int64_t)(n + 1) * dpad;
-  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
-    const int64_t p = e / dpad;
-    const int c = (int)(e - p * dpad);
+  const int64_t rows = (int64_t)n + 1;
+  const int32_t drow = (int32_t)blockDim.x / dpad, dc = (int32_t)blockDim.x - drow * dpad;
+  int64_t p = (int32_t)threadIdx.x / dpad;
+  int32_t c = (int32_t)threadIdx.x - (int32_t)p * dpad;
+  while (p < rows) {
     nodes[(dstart + p) * dpad + c] = c < d ? pts[(pstart + p) * d + c] : 0.0f;
+    p += drow;
+    c += dc;
+    if (c >= dpad) {
+      c -= dpad;
+      ++p;
+    }
   }
 }
 
