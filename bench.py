@@ -98,6 +98,30 @@ def measured_traffic():
     return rec["traffic_bytes"] if h == rec["source_hash"] else None
 
 
+def host_cpu():
+    """The host's CPU model (first "model name" line of /proc/cpuinfo) and its
+    logical CPU count."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def single_thread_rate(solve, xs, ys, lam, n=32):
+    """Cells/s of the oracle on one thread over the first n pairs of a sample."""
+    xs, ys = xs[:n], ys[:n]
+    t0 = time.perf_counter()
+    solve(xs, ys, lam, nthreads=1)
+    dt = time.perf_counter() - t0
+    cells = sum(((len(a) - 1) << lam) * ((len(b) - 1) << lam) for a, b in zip(xs, ys))
+    return cells / dt
+
+
 def cpu_baseline(X, Y, lam, n_sample, K_gpu, repeats=3, scheme="explicit"):
     """Time the FP64 oracle on the workload's pairs (all of them unless
     n_sample is given: a seeded sample), on all host threads, median of
@@ -125,7 +149,8 @@ def cpu_baseline(X, Y, lam, n_sample, K_gpu, repeats=3, scheme="explicit"):
             else f"{len(idx)} of the {nx * ny} Gram pairs (seeded)")
     return {"value": cells / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
             "sample": f"{what}, all host threads, median of {repeats} runs of {dt:.2f} s",
-            "gpu_max_err_on_sample": float(err.max())}
+            "gpu_max_err_on_sample": float(err.max()),
+            "single_thread_cells_per_s": single_thread_rate(solve, xs, ys, lam), **host_cpu()}
 
 
 def time_steps(fn, steps, warmup):
@@ -269,7 +294,9 @@ def bench_ragged(args):
             "value": scells / dt, "unit": "cells/s", "cores": oracle.max_threads(),
             "kind": "oracle", "sample": f"{len(idx)} of the 4096 pairs, all host threads, "
                                         f"{dt:.2f} s",
-            "gpu_max_err_on_sample": errs(got)["max"]}
+            "gpu_max_err_on_sample": errs(got)["max"],
+            "single_thread_cells_per_s": single_thread_rate(oracle.pairs, sx, sy, lam),
+            **host_cpu()}
         rec["err_vs_fp64_oracle"] = {"f32_increments": errs(got), "bf16_increments": errs(got16)}
     print(json.dumps(rec), flush=True)
 

@@ -1038,6 +1038,10 @@ sk_status sigkernel_increment_gram(const sk_paths* X, const sk_paths* Y, int32_t
   return e == hipSuccess ? SK_OK : SK_ERR_HIP;
 }
 
+static sk_status gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
+                               uint32_t flags, const float* dK, float* dX, float* dY, float* K,
+                               void* ws, size_t ws_bytes, void* stream);
+
 sk_status sigkernel_mmd2(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
                          uint32_t flags, float* mmd2, float* dX, void* ws, size_t ws_bytes,
                          void* stream) {
@@ -1059,13 +1063,17 @@ sk_status sigkernel_mmd2(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
   float* kxy = reinterpret_cast<float*>(base + L.kxy);
   void* sub = base + L.sub;
   const uint32_t unb = SK_SYMMETRIC | SK_NO_DIAG;
+  const bool grad = (flags & SK_MMD2_GRAD) != 0;
+  // with the gradient, Kxx and Kxy come from the backward's storing forwards
+  // (which sweep paths of at least two points)
+  const bool fused = grad && X->len >= 2 && Y->len >= 2;
   sk_status r;
-  if ((r = sigkernel_gram(X, X, dyadic_order, unb, kxx, sub, L.sub_bytes, stream))) return r;
+  if (!fused && (r = sigkernel_gram(X, X, dyadic_order, unb, kxx, sub, L.sub_bytes, stream)))
+    return r;
   if ((r = sigkernel_gram(Y, Y, dyadic_order, unb, kyy, sub, L.sub_bytes, stream))) return r;
-  if ((r = sigkernel_gram(X, Y, dyadic_order, 0, kxy, sub, L.sub_bytes, stream))) return r;
-  if (sk::launch_mmd2_reduce(kxx, X->n_paths, kyy, Y->n_paths, kxy, mmd2, st) != hipSuccess)
-    return SK_ERR_HIP;
-  if (flags & SK_MMD2_GRAD) {
+  if (!fused && (r = sigkernel_gram(X, Y, dyadic_order, 0, kxy, sub, L.sub_bytes, stream)))
+    return r;
+  if (grad) {
     const int64_t n = X->n_paths, m = Y->n_paths;
     float* wxx = reinterpret_cast<float*>(base + L.wxx);
     float* wxy = reinterpret_cast<float*>(base + L.wxy);
@@ -1077,21 +1085,26 @@ sk_status sigkernel_mmd2(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
       return SK_ERR_HIP;
     if (sk::launch_fill(wxy, n * m, (float)(-2.0 / ((double)n * (double)m)), st) != hipSuccess)
       return SK_ERR_HIP;
-    if ((r = sigkernel_gram_backward(X, X, dyadic_order, unb, wxx, dX, nullptr, sub, L.sub_bytes,
-                                     stream)))
+    if ((r = gram_backward(X, X, dyadic_order, unb, wxx, dX, nullptr, fused ? kxx : nullptr, sub,
+                           L.sub_bytes, stream)))
       return r;
-    if ((r = sigkernel_gram_backward(X, Y, dyadic_order, 0, wxy, tmp, nullptr, sub, L.sub_bytes,
-                                     stream)))
+    if ((r = gram_backward(X, Y, dyadic_order, 0, wxy, tmp, nullptr, fused ? kxy : nullptr, sub,
+                           L.sub_bytes, stream)))
       return r;
     if (sk::launch_add(dX, tmp, X->n_paths * X->len * X->dim, st) != hipSuccess)
       return SK_ERR_HIP;
   }
+  if (sk::launch_mmd2_reduce(kxx, X->n_paths, kyy, Y->n_paths, kxy, mmd2, st) != hipSuccess)
+    return SK_ERR_HIP;
   return SK_OK;
 }
 
-sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
-                                  uint32_t flags, const float* dK, float* dX, float* dY, void* ws,
-                                  size_t ws_bytes, void* stream) {
+// The Gram backward; K (optional) receives the forward values of the same
+// pairs, as sigkernel_gram with the same flags would write them (the storing
+// forward computes them anyway).
+static sk_status gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
+                               uint32_t flags, const float* dK, float* dX, float* dY, float* K,
+                               void* ws, size_t ws_bytes, void* stream) {
   if (!X || !Y) return SK_ERR_NULL;
   if (!valid_batch(X) || !valid_batch(Y)) return SK_ERR_SHAPE;
   if (X->dim != Y->dim) return SK_ERR_SHAPE;
@@ -1149,10 +1162,10 @@ sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t 
   fa.nx = X->n_paths;
   fa.ny = Y->n_paths;
   fa.mode = sym ? 2 : 1;
-  fa.no_diag = 0;
+  fa.no_diag = (K && (flags & SK_NO_DIAG)) ? 1 : 0;
   fa.run = (int32_t)P.run;
   fa.runs_per_row = P.runs_per_row;
-  fa.out = nullptr;
+  fa.out = K;
   fa.out_ld = Y->n_paths;
   fa.store = store;
   fa.store_stride = P.store_stride;
@@ -1199,6 +1212,12 @@ sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t 
       return SK_ERR_HIP;
   }
   return SK_OK;
+}
+
+sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
+                                  uint32_t flags, const float* dK, float* dX, float* dY, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  return gram_backward(X, Y, dyadic_order, flags, dK, dX, dY, nullptr, ws, ws_bytes, stream);
 }
 
 // ---- learned corrector ----------------------------------------------------

@@ -110,7 +110,8 @@ __device__ __forceinline__ void store_cells(float* __restrict__ p, const float (
 
 // Resolves the run of pairs (x_ia, y_b), b in [b0, b1), of wave w, writes the
 // value of every pair with nothing to sweep (a broken path: NaN; a one-point
-// path: the boundary value 1), and returns false when the wave has no
+// path: the boundary value 1; 0 on the diagonal of a symmetric Gram without
+// its diagonal, as for swept pairs), and returns false when the wave has no
 // columns to stream.  m: increments of x_ia; total: columns of the run.
 // Runs longer than one pair are only formed for uniform y batches, so every
 // pair of a run has the same width.
@@ -143,7 +144,7 @@ __device__ __forceinline__ bool wave_run(const SweepArgs& a, int64_t w, int lane
     if (!trivial) {
       total += nb;
     } else if (lane == 0) {
-      store_out(a, ia, b, v);
+      store_out(a, ia, b, (a.mode == 2 && a.no_diag && b == ia) ? 0.0f : v);
     }
   }
   if (m <= 0 || total == 0) return false;

@@ -88,3 +88,19 @@ def test_mmd2_full_size_value_and_fd_gradient():
         xm[i, c] -= h
         fd = (row_terms(xp) - row_terms(xm)) / (2 * h)
         assert abs(gpu[a, i, c] - fd) <= 1e-4 * np.abs(gpu).max() + 1e-4 * abs(fd), (a, i, c)
+
+
+@pytest.mark.parametrize("lam,L", [(0, 30), (2, 25), (4, 9), (1, 1)])
+def test_mmd2_value_same_with_and_without_gradient(lam, L):
+    """With the gradient, Kxx and Kxy come from the backward's storing
+    forwards (paths of at least two points) instead of separate Gram calls:
+    the same cells in the same order, so the value is bitwise the same."""
+    X = workloads.random_paths(15 + lam, 7, L, 3)
+    Y = workloads.random_paths(16 + lam, 5, L + (L > 1), 3)
+    val_g, dX = sk.sigkernel_mmd2(cuda(X), cuda(Y), lam, grad=True)
+    val, _ = sk.sigkernel_mmd2(cuda(X), cuda(Y), lam)
+    assert val_g.item() == val.item()
+    if L == 1:
+        assert val.item() == 0.0 and not dX.abs().any()
+    else:
+        assert abs(val.item() - oracle_mmd2(X, Y, lam)) <= 1e-6

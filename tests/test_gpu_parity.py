@@ -145,6 +145,25 @@ def test_symmetric_gram_and_no_diag():
     assert np.array_equal(nd[off], sym[off])
 
 
+@pytest.mark.parametrize("d", [3, 20])
+def test_symmetric_no_diag_covers_pairs_without_cells(d):
+    """One-point paths have nothing to sweep (value 1): without the diagonal
+    their diagonal entries are 0 too, in uniform and ragged batches (d = 20
+    runs the coefficient sweep)."""
+    one = torch.ones((4, 1, d), device="cuda")
+    nd = sk.sigkernel_gram(one, None, 1, symmetric=True, no_diag=True).cpu().numpy()
+    assert np.array_equal(nd, 1.0 - np.eye(4, dtype=np.float32))
+    lens = [1, 30, 1, 45, 2]
+    xs = [workloads.random_paths(606 + i, 1, L, d)[0] for i, L in enumerate(lens)]
+    X = RaggedPaths.from_list(xs, "cuda")
+    nd = sk.sigkernel_gram(X, None, 1, symmetric=True, no_diag=True).cpu().numpy()
+    ref = oracle.gram([x.astype(np.float64) for x in xs], [x.astype(np.float64) for x in xs], 1)
+    np.fill_diagonal(ref, 0.0)
+    assert np.all(np.diag(nd) == 0.0)
+    # the float32 inner products' rounding grows with the channels
+    assert mixed_err(nd, ref).max() <= TOL * max(1.0, np.sqrt(d / 16))
+
+
 def test_nan_propagates_to_its_own_pairs_only():
     X, Y = workloads.gram_batch(seed=505, n_x=4, n_y=3, n_points=30, dim=2)
     clean = sk.sigkernel_gram(cuda(X), cuda(Y), 1).cpu().numpy()
