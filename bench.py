@@ -153,14 +153,29 @@ def cpu_baseline(X, Y, lam, n_sample, K_gpu, repeats=3, scheme="explicit"):
             "single_thread_cells_per_s": single_thread_rate(solve, xs, ys, lam), **host_cpu()}
 
 
+SETTLE_S = 0.25  # untimed, synchronised repetitions of a step before its warm-up
+_settled = {"steps": 0}
+
+
 def time_steps(fn, steps, warmup):
-    """Run fn warmup + steps times; the timed steps run back to back between
+    """Run fn untimed until the device has executed it back to back for
+    SETTLE_S seconds (each repetition synchronised, so nothing queues up:
+    after the untimed set-up the GPU clocks take a few tens of milliseconds of
+    work to come up, and a short warm-up alone leaves the first timed steps
+    slow), then warmup + steps times; the timed steps run back to back between
     two synchronisations, with one HIP event pair on the launch stream around
     them.  Returns ([average step duration from the events, ms] * steps, wall
     seconds of the timed steps).  (Events around every single step would
     separate consecutive launches and add about a tenth of a millisecond per
     step on this hardware.)"""
     import torch
+    t_end = time.perf_counter() + SETTLE_S
+    n = 0
+    while n < 1 or time.perf_counter() < t_end:
+        fn()
+        torch.cuda.synchronize()
+        n += 1
+    _settled["steps"] += n
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -175,6 +190,12 @@ def time_steps(fn, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return [start.elapsed_time(end) / steps] * steps, wall
+
+
+def emit(rec):
+    """Print the JSON line, with the untimed settle repetitions it ran."""
+    rec["settle"] = {"seconds_per_timing": SETTLE_S, "steps": _settled["steps"]}
+    print(json.dumps(rec), flush=True)
 
 
 def make_step(call, capture, eager):
@@ -222,7 +243,7 @@ def bench_mmd(args):
                    "fine_cells_per_pair": cells},
         "avg_event_ms": float(np.mean(per)), "launch": launch,
     }
-    print(json.dumps(rec), flush=True)
+    emit(rec)
 
 
 def bench_ragged(args):
@@ -298,7 +319,7 @@ def bench_ragged(args):
             "single_thread_cells_per_s": single_thread_rate(oracle.pairs, sx, sy, lam),
             **host_cpu()}
         rec["err_vs_fp64_oracle"] = {"f32_increments": errs(got), "bf16_increments": errs(got16)}
-    print(json.dumps(rec), flush=True)
+    emit(rec)
 
 
 # FP64 operations counted for one double-precision exp: a two-constant range
@@ -386,7 +407,7 @@ def bench_lifted(args):
                                "sample": f"{what}, all host threads, median of 3 runs of "
                                          f"{dt:.2f} s",
                                "gpu_max_err_on_sample": float(err.max())}
-    print(json.dumps(rec), flush=True)
+    emit(rec)
 
 
 FIG3_LENGTHS = (10, 20, 50, 100, 200, 500, 1000, 2000)
@@ -459,7 +480,7 @@ def bench_fig3(args):
                                "kind": "oracle",
                                "sample": f"the same 5 pairs at length {longest['length']}, "
                                          "OpenMP over the pairs"}
-    print(json.dumps(rec), flush=True)
+    emit(rec)
 
 
 def bench_reduce(args):
@@ -516,7 +537,7 @@ def bench_reduce(args):
                                "sample": f"the whole experiment: Gram {tg * 1e3:.0f} ms (all "
                                          f"threads), search {ts * 1e3:.0f} ms (numpy)",
                                "selected_paths": np.nonzero(rb)[0].tolist(), "lam": rl}
-    print(json.dumps(rec), flush=True)
+    emit(rec)
 
 
 def bench_increment_gram(args):
@@ -547,7 +568,7 @@ def bench_increment_gram(args):
            "roofline": {"bound": "hbm", "achieved": recs["f32"]["hbm_GBps"], "peak": 8000.0,
                         "unit": "GB/s", "frac": recs["f32"]["frac_of_8TBps"], "traffic": None},
            "precisions": recs}
-    print(json.dumps(rec), flush=True)
+    emit(rec)
 
 
 def bench_corrector(args):
@@ -600,7 +621,7 @@ def bench_corrector(args):
                          "note": "whole predict call time; the fused network kernel's own "
                                  "duration is in profiles/"},
     }
-    print(json.dumps(rec), flush=True)
+    emit(rec)
 
 
 def copy_calibration(args):
@@ -720,7 +741,7 @@ def main():
         n_sample = args.cpu_sample_pairs
         rec["cpu_baseline"] = cpu_baseline(X, Y, lam, n_sample, out.cpu().numpy(),
                                           scheme=scheme)
-    print(json.dumps(rec), flush=True)
+    emit(rec)
 
 
 if __name__ == "__main__":

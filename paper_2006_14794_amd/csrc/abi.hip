@@ -350,9 +350,9 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam0, float* o
   pp.npairs = (int32_t)npairs;
   pp.gram_ny = gram ? Y->n_paths : 0;
   pp.lam = lam;
-  // pipelined bands: every pair with cells joins the band-task queue (a short
-  // pair is one task at the end of it), so the short class keeps only the
-  // pairs without cells
+  // pipelined bands: every pair joins the band-task queue (a short pair, or
+  // one without cells, is one task at the end of it) and there is no short
+  // class
   const bool pipe = PL.pipe && tune.pair_bands != 1;
   pp.rows_lo = pipe ? 0 : PL.rows_lo;
   pp.rows_hi = PL.rows_hi;
@@ -401,7 +401,7 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam0, float* o
   } else {
     e = sk::launch_pairs(a, lam, PL.rows_hi, d, PL.slots, stream, tune.pair_blocks_per_cu);
   }
-  if (e == hipSuccess) {
+  if (e == hipSuccess && !pipe) {
     // the short class follows the long one in `order`; its offset (the long
     // class's count) is only known on the device, where the kernel reads it
     a.order = order;

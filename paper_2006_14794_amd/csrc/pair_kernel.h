@@ -48,7 +48,10 @@ __global__ __launch_bounds__(256) void pair_kernel(const PairArgs a) {
     const int64_t iy = a.gram_ny ? pid - ix * a.gram_ny : pid;
     const int32_t mx = n_inc(a.x_n, a.x_len, ix), my = n_inc(a.y_n, a.y_len, iy);
     if (mx < 0 || my < 0 || mx == 0 || my == 0) {
-      if (lane == 0) a.out[pid] = (mx < 0 || my < 0) ? __builtin_nanf("") : 1.0f;
+      // every lane stores the same value: a lane-0-only store before the
+      // continue has let waves re-enter this loop with a partial exec mask
+      // (and sweep an earlier task again) with this compiler
+      a.out[pid] = (mx < 0 || my < 0) ? __builtin_nanf("") : 1.0f;
       continue;
     }
     const bool swap = mx > my;
@@ -229,7 +232,8 @@ __global__ __launch_bounds__(256) void pair_band_kernel(const PairArgs a) {
     const int64_t iy = a.gram_ny ? pid - ix * a.gram_ny : pid;
     const int32_t mx = n_inc(a.x_n, a.x_len, ix), my = n_inc(a.y_n, a.y_len, iy);
     if (mx <= 0 || my <= 0) {  // one task for such a pair
-      if (lane == 0) a.out[pid] = (mx < 0 || my < 0) ? __builtin_nanf("") : 1.0f;
+      // every lane stores the same value (see pair_kernel)
+      a.out[pid] = (mx < 0 || my < 0) ? __builtin_nanf("") : 1.0f;
       continue;
     }
     const bool swap = mx > my;

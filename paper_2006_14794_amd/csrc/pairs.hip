@@ -30,7 +30,9 @@ __global__ __launch_bounds__(1024) void pair_plan_kernel(
     const int32_t mx = incs(x_n, x_len, ix), my = incs(y_n, y_len, iy);
     if (mx <= 0 || my <= 0) {
       cost = 0;
-      return 0;  // trivial or broken: instant, short class
+      // trivial or broken: instant; the short class, or the end of the long
+      // one when there is no short class (rows_lo = 0)
+      return rows_lo > 0 ? 0 : 1;
     }
     const int64_t mn = mx < my ? mx : my, mxn = mx < my ? my : mx;
     const int64_t M = mn << lam;

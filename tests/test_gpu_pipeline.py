@@ -127,3 +127,21 @@ def test_graph_replays_refill_the_slots():
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy(), eager), i
         sk.sigkernel_pair(Xt[:1], Yt[:1], 0)  # other work between replays
+
+
+def test_repeated_calls_with_pairs_without_cells():
+    """Pairs without cells are single tasks at the end of the band queue.
+    Written by one lane before the loop's continue, they once let a wave
+    sweep an earlier band again with part of its lanes, corrupting the first
+    pair's hand-over in some calls: every repeat must equal the sequential
+    bands."""
+    rng = np.random.default_rng(580)
+    lx = rng.integers(60, 700, 1300)
+    ly = rng.integers(60, 700, 1300)
+    lx[::97] = 1
+    xs = [workloads.random_paths(581 + i, 1, int(L), 2)[0] for i, L in enumerate(lx)]
+    ys = [workloads.random_paths(5000 + i, 1, int(L), 2)[0] for i, L in enumerate(ly)]
+    X, Y = RaggedPaths.from_list(xs, "cuda"), RaggedPaths.from_list(ys, "cuda")
+    ref = sequential(X, Y, 3)
+    for i in range(6):
+        assert np.array_equal(sk.sigkernel_pair(X, Y, 3).cpu().numpy(), ref), i
