@@ -242,7 +242,38 @@ def bench_mmd(args):
                    "forward_pairs": fwd_pairs, "adjoint_pairs": bwd_pairs,
                    "fine_cells_per_pair": cells},
         "avg_event_ms": float(np.mean(per)), "launch": launch,
+        # the adjoint's cell sums: 4 bytes written by the storing forward and
+        # read back by the adjoint per adjoint fine cell (inputs and outputs
+        # are a few MB)
+        "roofline": {"bound": "hbm", "achieved": 8.0 * bwd_pairs * cells / (np.mean(per) / 1e3) / 1e9,
+                     "peak": 8000.0, "unit": "GB/s",
+                     "frac": 8.0 * bwd_pairs * cells / (np.mean(per) / 1e3) / 1e9 / 8000.0,
+                     "traffic": None,
+                     "kernel": "storing forward + adjoint (events around the timed steps)",
+                     "bytes_per_adjoint_cell": 8},
     }
+    if not args.no_cpu_baseline:
+        import oracle
+        ns = 16  # the first 16 generated and 16 target paths: the same estimator and gradient
+        Xs, Ys = X[:ns].astype(np.float64), Y[:ns].astype(np.float64)
+        threads = oracle.max_threads()
+        t0 = time.perf_counter()
+        Kxx = oracle.gram(Xs, Xs, lam, nthreads=threads)
+        Kyy = oracle.gram(Ys, Ys, lam, nthreads=threads)
+        Kxy = oracle.gram(Xs, Ys, lam, nthreads=threads)
+        oracle.mmd2_unbiased(Kxx, Kyy, Kxy)
+        wxx, _, wxy = oracle.mmd2_weights(ns, ns)
+        oracle.gram_backward(Xs, Xs, wxx, lam, nthreads=threads)
+        oracle.gram_backward(Xs, Ys, wxy, lam, nthreads=threads)
+        dt = time.perf_counter() - t0
+        # the oracle solves full Gram blocks (both halves of the symmetric ones)
+        # and both backward blocks in full: count the cells it actually sweeps
+        s_cells = (3 * ns * ns + 2 * ns * ns) * cells
+        rec["cpu_baseline"] = {
+            "value": s_cells / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"MMD^2 value and gradient of the first {ns} vs {ns} paths (full Gram "
+                      f"blocks and full backward blocks, {s_cells:.3g} cells), all host threads, "
+                      f"{dt:.2f} s", **host_cpu()}
     emit(rec)
 
 
