@@ -150,7 +150,8 @@ sk_status sigkernel_gram(const sk_paths *X, const sk_paths *Y, int32_t dyadic_or
  *    forward) carry no gradient.
  *  - Uniform batches only (ragged offsets give SK_ERR_UNSUPPORTED).
  *  - Workspace: sigkernel_workspace_bytes(SK_OP_GRAM_BACKWARD, ...); the
- *    forward cell sums of at most 4 GiB worth of pairs are stored at a time.
+ *    forward cell sums (4 bytes per fine cell and pipeline step) of at most
+ *    24 GiB worth of pairs are stored at a time, in equal chunks.
  */
 sk_status sigkernel_gram_backward(const sk_paths *X, const sk_paths *Y, int32_t dyadic_order,
                                   uint32_t flags, const float *dK, float *dX, float *dY,

@@ -242,7 +242,9 @@ size_t gram_ws(const sk_paths* X, const sk_paths* Y, int32_t lam) {
 
 // Backward workspace: the forward layout, then the per-wave store of one
 // chunk of waves, the per-run x-side and per-pair y-side increment gradients.
-constexpr size_t kStoreCapBytes = size_t(4) << 30;
+// The store of a chunk is capped (HBM holds 288 GB); the waves are split into
+// chunks of equal size, so that every launch still fills the chip.
+constexpr size_t kStoreCapBytes = size_t(24) << 30;
 
 struct BackwardPlan {
   int R, waves_per_block;
@@ -275,9 +277,10 @@ BackwardPlan backward_plan(const sk_paths* X0, const sk_paths* Y0, int32_t lam0,
   const int64_t rs = (int64_t)P.R << lam;
   P.store_stride = sk::sweep_steps(P.run * (n > 0 ? n : 1)) * 64 * rs;
   const int64_t per_wave = P.store_stride * (int64_t)sizeof(float);
-  P.chunk = (int64_t)(kStoreCapBytes / (size_t)per_wave);
-  if (P.chunk < 1) P.chunk = 1;
-  if (P.chunk > P.n_waves) P.chunk = P.n_waves;
+  int64_t fit = (int64_t)(kStoreCapBytes / (size_t)per_wave);
+  if (fit < 1) fit = 1;
+  const int64_t nchunks = (P.n_waves + fit - 1) / fit;
+  P.chunk = nchunks > 0 ? (P.n_waves + nchunks - 1) / nchunks : 1;
   size_t off = forward_ws(X, Y);
   P.store_off = off;
   off += align256((size_t)P.chunk * (size_t)per_wave);
