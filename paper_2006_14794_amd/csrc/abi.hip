@@ -274,7 +274,7 @@ BackwardPlan backward_plan(const sk_paths* X0, const sk_paths* Y0, int32_t lam0,
   P.run = choose_run(X->n_paths, Y->n_paths, t.run);
   P.runs_per_row = (Y->n_paths + P.run - 1) / P.run;
   P.n_waves = X->n_paths * P.runs_per_row;
-  const int64_t rs = (int64_t)P.R << lam;
+  const int64_t rs = sk::cell_group_floats(P.R << lam);
   P.store_stride = sk::sweep_steps(P.run * (n > 0 ? n : 1)) * 64 * rs;
   const int64_t per_wave = P.store_stride * (int64_t)sizeof(float);
   int64_t fit = (int64_t)(kStoreCapBytes / (size_t)per_wave);

@@ -117,10 +117,10 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const BwdArgs a) {
   // forward handled it at its step gcol + lane
   int32_t gcol = total + 62 - lane;
   const float* __restrict__ yp = a.incy + ((int64_t)b0 * n + gcol) * DP;
-  const float* __restrict__ sbase = a.store + (w - a.wave0) * a.store_stride + (int64_t)lane * RS;
+  const float* __restrict__ sbase = a.store + (w - a.wave0) * a.store_stride + (int64_t)lane * 4;
   auto srow = [&](int32_t tf) -> const float* {  // clamped: inactive steps read in bounds
     const int32_t c = tf < 0 ? 0 : (tf >= nsteps ? nsteps - 1 : tf);
-    return sbase + (int64_t)c * 64 * RS;
+    return sbase + (int64_t)c * 64 * cell_group_floats(RS);
   };
 
   double ar[R];     // a of this strip's cells at the first fine column of the next coarse column
@@ -156,12 +156,12 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const BwdArgs a) {
   float dyA[DP], dyB[DP];
   float sA[RS], sB[RS];
   load_vec<DP>(yp, dyA);
-  load_vec<RS>(srow(gcol + lane), sA);
+  get_cells<RS>(srow(gcol + lane), sA);
 
   auto step = [&](float (&dy)[DP], float (&dyn)[DP], float (&sv)[RS], float (&svn)[RS]) {
     // refill the other buffers for the next step (consumed by the previous one)
     load_vec<DP>(yp - DP, dyn);
-    load_vec<RS>(srow(gcol + lane - 1), svn);
+    get_cells<RS>(srow(gcol + lane - 1), svn);
 
     float h32[CR + 1];
 #pragma unroll

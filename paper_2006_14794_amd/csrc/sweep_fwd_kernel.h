@@ -95,19 +95,6 @@ __device__ __forceinline__ void store_out(const SweepArgs& a, int64_t ia, int64_
   }
 }
 
-// R*S consecutive floats of one lane (16-byte aligned when N % 4 == 0)
-template <int N>
-__device__ __forceinline__ void store_cells(float* __restrict__ p, const float (&v)[N]) {
-  if constexpr (N % 4 == 0) {
-#pragma unroll
-    for (int i = 0; i < N; i += 4)
-      *reinterpret_cast<float4*>(p + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
-  } else {
-#pragma unroll
-    for (int i = 0; i < N; ++i) p[i] = v[i];
-  }
-}
-
 // Resolves the run of pairs (x_ia, y_b), b in [b0, b1), of wave w, writes the
 // value of every pair with nothing to sweep (a broken path: NaN; a one-point
 // path: the boundary value 1; 0 on the diagonal of a symmetric Gram without
@@ -249,9 +236,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     up[cc] = 1.0;  // lane 0 keeps the boundary value for the whole run
   }
   double up_last = 1.0;
-  // backward support: S = A + B of every cell, per step, lane-contiguous
+  // backward support: S = A + B of every cell, per step, groups of four
+  // floats interleaved across the lanes (cell_group_floats)
   float* __restrict__ sp = nullptr;
-  if constexpr (STORE) sp = a.store + (w - a.wave0) * a.store_stride + (int64_t)lane * (R * S);
+  if constexpr (STORE) sp = a.store + (w - a.wave0) * a.store_stride + (int64_t)lane * 4;
 
   float dyA[DP], dyB[DP], dyC[DP];
   load_row<DP>(yp, dyA);
@@ -286,7 +274,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
       double v[R][S];
       float sv[STORE ? R * S : 1];
       cell_block<R, LAM, CR, STORE>(v, sv, u, up, up_last, gk);
-      if constexpr (STORE) store_cells<R * S>(sp, sv);
+      if constexpr (STORE) put_cells<R * S>(sp, sv);
 #pragma unroll
       for (int r = 0; r < R; ++r) u[r] = v[r][S - 1];
 #pragma unroll
@@ -307,7 +295,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     }
     ++g;
     yp += DP;
-    if constexpr (STORE) sp += 64 * (R * S);
+    if constexpr (STORE) sp += 64 * cell_group_floats(R * S);
   };
 
   for (int32_t t = 0; t < nsteps; t += 3) {
