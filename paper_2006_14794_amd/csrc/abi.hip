@@ -399,8 +399,17 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam0, float* o
     b.task_counter = counts + 4;
     b.tbuf = tbuf;
     b.tstride = PL.band_stride;
+    // a batch of equal lengths has one top band for all its pairs: when it
+    // needs all R rows per lane, the kernel with bands of one height runs
+    bool fit_top = true;
+    if (!X->offsets && !Y->offsets) {
+      const int64_t band_rows = 64 * (int64_t)PL.rows_hi;
+      const int64_t M = (int64_t)((Xr.len < Yr.len ? Xr.len : Yr.len) - 1) << lam;
+      const int64_t top_rows = M - (M - 1) / band_rows * band_rows;
+      fit_top = 2 * top_rows <= band_rows;
+    }
     e = sk::launch_pair_bands(b, lam, PL.rows_hi, d, (PL.tasks_max + 3) & ~int64_t(3), stream,
-                              tune.pair_blocks_per_cu);
+                              tune.pair_blocks_per_cu, fit_top);
   } else {
     e = sk::launch_pairs(a, lam, PL.rows_hi, d, PL.slots, stream, tune.pair_blocks_per_cu);
   }

@@ -12,6 +12,16 @@ constexpr bool sweep_fits(int R, int LAM, int D) {
   return ((R >> LAM) > 0 ? (R >> LAM) : 1) * D <= 96 && R <= 32;
 }
 
+// Largest power-of-two rows per lane (at most 32) that sweep_fits allows.
+// The pipelined band kernel only runs when the tallest grid needs several
+// bands, which happens only at this height, so it is compiled at it alone.
+constexpr int max_fitting_rows(int LAM, int D) {
+  int r = 0;
+  for (int R = 1; R <= 32; R *= 2)
+    if (sweep_fits(R, LAM, D)) r = R;
+  return r;
+}
+
 // The adjoint keeps a second x-increment row, the gradient accumulators and
 // the stored cell sums in registers as well: a tighter budget (no spills).
 constexpr bool adjoint_fits(int R, int LAM, int D) {

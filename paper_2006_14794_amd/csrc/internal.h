@@ -160,12 +160,16 @@ struct PairPlanArgs {
 hipError_t launch_pair_plan(const PairPlanArgs& p, hipStream_t stream);
 // Band tasks of the long class (order[0 .. counts[0])): task_base[k] = sum of
 // the band counts (rows / (64 R), rounded up) of the pairs before k, the total
-// at task_base[counts[0]]; zeroes *task_counter.  counts[0] <= 1024.
+// at task_base[counts[0]]; zeroes *task_counter.  One workgroup, any count.
 hipError_t launch_band_plan(const PairPlanArgs& p, int rows_per_lane, int32_t* task_base,
                             int32_t* task_counter, hipStream_t stream);
-// The pipelined band kernel over those tasks (persistent, like launch_pairs).
+// The pipelined band kernel over those tasks (persistent, like launch_pairs),
+// compiled only at the largest rows per lane that fits.  fit_top: each pair's
+// top band takes R/4, R/2 or R rows per lane by its rows; else every band
+// takes R.
 hipError_t launch_pair_bands(const PairArgs& a, int lam, int rows_per_lane, int dim,
-                             int64_t max_waves, hipStream_t stream, int blocks_per_cu = 0);
+                             int64_t max_waves, hipStream_t stream, int blocks_per_cu,
+                             bool fit_top);
 // p[0 .. n) = v (64-bit pattern), as a kernel
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t stream);
 // kBandSlotSentinel into the slot buffers of the tasks a band plan numbered
@@ -245,7 +249,8 @@ hipError_t launch_gram_mfma(const GramArgs& a, int precision, hipStream_t stream
 // Compiled sweep kernels by kind, dyadic order, rows per lane and channels
 // (nullptr when the configuration is not compiled).
 enum { kKernelForward = 0, kKernelForwardStore = 1, kKernelAdjoint = 2, kKernelPair = 3,
-       kKernelLifted = 4, kKernelForwardImplicit = 5, kKernelPairBand = 6 };
+       kKernelLifted = 4, kKernelForwardImplicit = 5, kKernelPairBand = 6,
+       kKernelPairBandFull = 7 };
 void* sweep_fn(int kind, int lam, int rows_per_lane, int dim);
 
 }  // namespace sk

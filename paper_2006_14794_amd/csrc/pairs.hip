@@ -216,9 +216,9 @@ hipError_t launch_pairs(const PairArgs& a, int lam, int R, int d, int64_t max_wa
 }
 
 hipError_t launch_pair_bands(const PairArgs& a, int lam, int R, int d, int64_t max_waves,
-                             hipStream_t stream, int blocks_per_cu_wanted) {
-  return launch_persistent(kKernelPairBand, a, lam, R, d, max_waves, stream,
-                           blocks_per_cu_wanted);
+                             hipStream_t stream, int blocks_per_cu_wanted, bool fit_top) {
+  return launch_persistent(fit_top ? kKernelPairBand : kKernelPairBandFull, a, lam, R, d,
+                           max_waves, stream, blocks_per_cu_wanted);
 }
 
 }  // namespace sk

@@ -12,19 +12,21 @@ SK_DECL(3, 0) SK_DECL(3, 1) SK_DECL(3, 2) SK_DECL(3, 3)
 SK_DECL(4, 0) SK_DECL(4, 1) SK_DECL(4, 2) SK_DECL(4, 3)
 SK_DECL(5, 0) SK_DECL(5, 1) SK_DECL(5, 2) SK_DECL(5, 3)
 SK_DECL(6, 0) SK_DECL(6, 1) SK_DECL(6, 2) SK_DECL(6, 3)
+SK_DECL(7, 0) SK_DECL(7, 1) SK_DECL(7, 2) SK_DECL(7, 3)
 #undef SK_DECL
 
 void* sweep_fn(int kind, int lam, int R, int d) {
   using Pick = void* (*)(int, int);
-  static const Pick table[7][4] = {
+  static const Pick table[8][4] = {
       {sweep_fn_k0_l0_, sweep_fn_k0_l1_, sweep_fn_k0_l2_, sweep_fn_k0_l3_},
       {sweep_fn_k1_l0_, sweep_fn_k1_l1_, sweep_fn_k1_l2_, sweep_fn_k1_l3_},
       {sweep_fn_k2_l0_, sweep_fn_k2_l1_, sweep_fn_k2_l2_, sweep_fn_k2_l3_},
       {sweep_fn_k3_l0_, sweep_fn_k3_l1_, sweep_fn_k3_l2_, sweep_fn_k3_l3_},
       {sweep_fn_k4_l0_, sweep_fn_k4_l1_, sweep_fn_k4_l2_, sweep_fn_k4_l3_},
       {sweep_fn_k5_l0_, sweep_fn_k5_l1_, sweep_fn_k5_l2_, sweep_fn_k5_l3_},
-      {sweep_fn_k6_l0_, sweep_fn_k6_l1_, sweep_fn_k6_l2_, sweep_fn_k6_l3_}};
-  if (kind < 0 || kind > 6 || lam < 0 || lam > 3) return nullptr;
+      {sweep_fn_k6_l0_, sweep_fn_k6_l1_, sweep_fn_k6_l2_, sweep_fn_k6_l3_},
+      {sweep_fn_k7_l0_, sweep_fn_k7_l1_, sweep_fn_k7_l2_, sweep_fn_k7_l3_}};
+  if (kind < 0 || kind > 7 || lam < 0 || lam > 3) return nullptr;
   return table[kind][lam](R, d);
 }
 

@@ -1,10 +1,11 @@
 // Instantiations of one sweep kernel (SK_KIND: forward, forward with store,
-// adjoint, persistent pairs, lifted forward, implicit forward, pipelined bands) at one dyadic order SK_LAM.  Included by sweep_k{kind}_l{lam}.hip
+// adjoint, persistent pairs, lifted forward, implicit forward, pipelined bands
+// with a fitted top band, pipelined bands of one height) at one dyadic order SK_LAM.  Included by sweep_k{kind}_l{lam}.hip
 // so that the configurations compile in parallel translation units.
 #include "dispatch.h"
 #if SK_KIND == 2
 #include "sweep_bwd_kernel.h"
-#elif SK_KIND == 3 || SK_KIND == 6
+#elif SK_KIND == 3 || SK_KIND == 6 || SK_KIND == 7
 #include "pair_kernel.h"
 #elif SK_KIND == 4
 #include "lifted_kernel.h"
@@ -51,13 +52,13 @@ struct Pair {
       return nullptr;
   }
 };
-#elif SK_KIND == 6
+#elif SK_KIND == 6 || SK_KIND == 7
 struct PairBand {
   using Fn = void*;
   template <int R, int LAM, int D>
   static Fn get() {
-    if constexpr (sweep_fits(R, LAM, D))
-      return reinterpret_cast<void*>(&pairk::pair_band_kernel<R, LAM, D>);
+    if constexpr (sweep_fits(R, LAM, D) && R == max_fitting_rows(LAM, D))
+      return reinterpret_cast<void*>(&pairk::pair_band_kernel<R, LAM, D, SK_KIND == 6>);
     else
       return nullptr;
   }
@@ -124,6 +125,8 @@ void* SK_CAT(SK_CAT(sweep_fn_k4_l, SK_LAM), _)(int R, int d) { return pick_fixed
 void* SK_CAT(SK_CAT(sweep_fn_k5_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<FwdImplicit>(R, d); }
 #elif SK_KIND == 6
 void* SK_CAT(SK_CAT(sweep_fn_k6_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<PairBand>(R, d); }
+#elif SK_KIND == 7
+void* SK_CAT(SK_CAT(sweep_fn_k7_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<PairBand>(R, d); }
 #else
 void* SK_CAT(SK_CAT(sweep_fn_k2_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Adjoint>(R, d); }
 #endif

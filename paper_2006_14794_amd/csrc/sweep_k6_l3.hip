@@ -1,4 +1,4 @@
-// Sweep kernel instantiations: pipelined row bands of few long pairs, dyadic order 3 (see sweep_inst.h).
+// Sweep kernel instantiations: pipelined row bands with a fitted top band, dyadic order 3 (see sweep_inst.h).
 #define SK_KIND 6
 #define SK_LAM 3
 #include "sweep_inst.h"

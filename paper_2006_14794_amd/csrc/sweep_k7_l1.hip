@@ -1,0 +1,5 @@
+// Sweep kernel instantiations: pipelined bands of one height, dyadic order 1
+// (see sweep_inst.h).
+#define SK_KIND 7
+#define SK_LAM 1
+#include "sweep_inst.h"

@@ -79,6 +79,28 @@ def test_ragged_mix_of_long_short_and_degenerate():
     assert np.array_equal(got, sequential(X, Y, 2))
 
 
+# d = 16 at dyadic order 2 runs full bands of 16 fine rows per lane (256
+# increments on the rows); the top band takes 4, 8 or 16 rows per lane by the
+# rows left over.  Shorter-path increments m around every switch: one band
+# (64 | 65, 128 | 129, 256), two bands (257, 320 | 321, 384 | 385, 512) and
+# three (600); half the pairs put the shorter path on y.
+TOP_BAND_M = [64, 65, 128, 129, 256, 257, 320, 321, 384, 385, 512, 600]
+
+
+def test_top_band_heights():
+    xs, ys = [], []
+    for i, m in enumerate(TOP_BAND_M):
+        a = workloads.random_paths(560 + i, 1, m + 1, 16)[0]
+        b = workloads.random_paths(580 + i, 1, m + 1 + 23 * (i % 3), 16)[0]
+        xs.append(a if i % 2 == 0 else b)
+        ys.append(b if i % 2 == 0 else a)
+    X, Y = RaggedPaths.from_list(xs, "cuda"), RaggedPaths.from_list(ys, "cuda")
+    got = sk.sigkernel_pair(X, Y, 2).cpu().numpy()
+    ref = oracle.pairs([f64(a) for a in xs], [f64(b) for b in ys], 2)
+    assert mixed_err(got, ref).max() <= TOL
+    assert np.array_equal(got, sequential(X, Y, 2))
+
+
 def test_more_pairs_than_one_scan_chunk():
     """1500 uniform pairs of two bands each: the band plan numbers the tasks
     over two 1024-pair chunks of its scan."""
