@@ -390,9 +390,9 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam0, float* o
     double* tbuf = reinterpret_cast<double*>(base + PL.tbuf);
     if (sk::launch_band_plan(pp, PL.rows_hi, task_base, counts + 4, stream) != hipSuccess)
       return SK_ERR_HIP;
-    if (sk::launch_fill_task_slots(reinterpret_cast<uint64_t*>(tbuf), task_base, counts,
-                                   PL.band_stride, PL.tasks_max * PL.band_stride,
-                                   sk::kBandSlotSentinel, stream) != hipSuccess)
+    if (sk::launch_fill_task_slots(reinterpret_cast<uint64_t*>(tbuf), pp, task_base,
+                                   PL.band_stride, PL.tasks_max, sk::kBandSlotSentinel,
+                                   stream) != hipSuccess)
       return SK_ERR_HIP;
     sk::PairArgs b = a;
     b.task_base = task_base;

@@ -172,10 +172,11 @@ hipError_t launch_pair_bands(const PairArgs& a, int lam, int rows_per_lane, int 
                              bool fit_top);
 // p[0 .. n) = v (64-bit pattern), as a kernel
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t stream);
-// kBandSlotSentinel into the slot buffers of the tasks a band plan numbered
-// (reads task_base[counts[0]] on the device; at most n_max elements).
-hipError_t launch_fill_task_slots(uint64_t* tbuf, const int32_t* task_base,
-                                  const int32_t* counts, int64_t stride, int64_t n_max,
+// v (kBandSlotSentinel) into the slots the band tasks of a band plan will
+// write: the first (columns << lam) doubles of every task but each pair's
+// last, tasks below t_max only (reads the plan on the device).
+hipError_t launch_fill_task_slots(uint64_t* tbuf, const PairPlanArgs& p,
+                                  const int32_t* task_base, int64_t stride, int64_t t_max,
                                   uint64_t v, hipStream_t stream);
 // The sentinel of the pipelined bands' slots (a signalling NaN arithmetic never yields).
 constexpr uint64_t kBandSlotSentinel = 0x7FF40000DEAD5EB0ull;

@@ -7,23 +7,31 @@
 namespace sk {
 namespace {
 
-constexpr int kSortMax = 8192;  // pairs sorted in one workgroup's LDS
+constexpr int kBuckets = 1024;  // cost buckets per class
 
 __device__ __forceinline__ int32_t incs(const int32_t* plan, int32_t len, int64_t k) {
   return plan ? plan[k] : len - 1;
 }
 
 // One workgroup.  Output: order[0 .. c_hi) = long-row class, order[c_hi ..
-// c_hi + c_lo) = short-row class, each by decreasing estimated cost; counts
-// {c_hi, c_lo}; both queue counters zeroed.
+// c_hi + c_lo) = short-row class, each roughly by decreasing estimated cost
+// (a counting sort into kBuckets equal cost ranges per class; the order
+// within a bucket is whatever the atomics give, which only affects
+// scheduling); counts {c_hi, c_lo}; both queue counters zeroed.
 __global__ __launch_bounds__(1024) void pair_plan_kernel(
     const int32_t* __restrict__ x_n, int32_t x_len, const int32_t* __restrict__ y_n,
     int32_t y_len, int32_t npairs, int32_t lam, int32_t rows_lo, int32_t rows_hi,
     int64_t gram_ny, int32_t* __restrict__ order, int32_t* __restrict__ counts,
     int32_t* __restrict__ counters) {
-  __shared__ unsigned long long keys[kSortMax];
+  __shared__ int32_t hist[2 * kBuckets];  // bucket 0 .. kBuckets-1: long class
   __shared__ int32_t cnt[2];
-  if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+  __shared__ unsigned long long cmax[2];
+  __shared__ int32_t wsum[16];
+  for (int i = threadIdx.x; i < 2 * kBuckets; i += blockDim.x) hist[i] = 0;
+  if (threadIdx.x < 2) {
+    cnt[threadIdx.x] = 0;
+    cmax[threadIdx.x] = 0;
+  }
   __syncthreads();
   auto classify = [&](int32_t k, unsigned long long& cost) -> int {
     const int64_t ix = gram_ny ? k / gram_ny : k, iy = gram_ny ? k - ix * gram_ny : k;
@@ -40,62 +48,50 @@ __global__ __launch_bounds__(1024) void pair_plan_kernel(
     const int64_t band_rows = 64 * (int64_t)(cls ? rows_hi : rows_lo);
     const int64_t bands = (M + band_rows - 1) / band_rows;
     cost = (unsigned long long)(bands * (mxn + 63));
+    if (cost > (1ull << 45) - 1) cost = (1ull << 45) - 1;
     return cls;
   };
-  if (npairs <= kSortMax) {
-    int n2 = 1;
-    while (n2 < npairs) n2 <<= 1;
-    for (int32_t k = threadIdx.x; k < n2; k += blockDim.x) {
-      unsigned long long key = 0;  // padding sorts last
-      if (k < npairs) {
-        unsigned long long cost;
-        const int cls = classify(k, cost);
-        if (cost > (1ull << 45) - 1) cost = (1ull << 45) - 1;
-        // descending: long class first, then cost, then ascending index
-        key = (1ull << 63) | ((unsigned long long)cls << 62) | (cost << 16) |
-              (unsigned long long)(65535 - k);
-        atomicAdd(&cnt[cls], 1);
-      }
-      keys[k] = key;
+  // bucket of a pair: long class first, each class by decreasing cost
+  auto bucket = [&](int cls, unsigned long long cost) -> int {
+    const unsigned long long q = cost * kBuckets / (cmax[cls] + 1);  // 0 .. kBuckets-1
+    return (cls ? 0 : kBuckets) + (kBuckets - 1 - (int)q);
+  };
+  for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x) {
+    unsigned long long cost;
+    const int cls = classify(k, cost);
+    atomicAdd(&cnt[cls], 1);
+    atomicMax(&cmax[cls], cost);
+  }
+  __syncthreads();
+  for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x) {
+    unsigned long long cost;
+    const int cls = classify(k, cost);
+    atomicAdd(&hist[bucket(cls, cost)], 1);
+  }
+  __syncthreads();
+  // exclusive scan of the 2 kBuckets counts: two per thread, then across waves
+  {
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int32_t a0 = hist[2 * t], a1 = hist[2 * t + 1];
+    int32_t v = a0 + a1;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t u = __shfl_up(v, o, 64);
+      if (lane >= o) v += u;
     }
+    if (lane == 63) wsum[wid] = v;
     __syncthreads();
-    // bitonic sort, descending
-    for (int size = 2; size <= n2; size <<= 1) {
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-          const int j = i ^ stride;
-          if (j > i) {
-            const bool desc = (i & size) == 0;
-            const unsigned long long a = keys[i], b = keys[j];
-            if ((a < b) == desc) {
-              keys[i] = b;
-              keys[j] = a;
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
-    for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x)
-      order[k] = 65535 - (int32_t)(keys[k] & 0xFFFFull);
-  } else {
-    // large batches: class compaction without ordering
-    __shared__ int32_t pos[2];
-    for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x) {
-      unsigned long long cost;
-      atomicAdd(&cnt[classify(k, cost)], 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      pos[1] = 0;
-      pos[0] = cnt[1];
-    }
-    __syncthreads();
-    for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x) {
-      unsigned long long cost;
-      const int cls = classify(k, cost);
-      order[atomicAdd(&pos[cls], 1)] = k;
-    }
+    int32_t before = 0;
+    for (int w = 0; w < wid; ++w) before += wsum[w];
+    const int32_t start = before + v - (a0 + a1);
+    hist[2 * t] = start;
+    hist[2 * t + 1] = start + a0;
+  }
+  __syncthreads();
+  for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x) {
+    unsigned long long cost;
+    const int cls = classify(k, cost);
+    order[atomicAdd(&hist[bucket(cls, cost)], 1)] = k;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -149,16 +145,31 @@ __global__ __launch_bounds__(1024) void band_plan_kernel(
   }
 }
 
-// The sentinel in the slot buffers of the tasks the band plan numbered
-// (task_base[count] of them, at most n_max / stride).
+// The sentinel into the part of the slot buffers that the bands write: the
+// first n S doubles (n coarse columns of the pair, S fine columns each) of
+// every band task but a pair's last, which hands nothing on.  One workgroup
+// per pair of the band plan; tasks at or past t_max are left alone.
 __global__ __launch_bounds__(256) void fill_task_slots_kernel(
     uint64_t* __restrict__ tbuf, const int32_t* __restrict__ task_base,
-    const int32_t* __restrict__ counts, int64_t stride, int64_t n_max, uint64_t v) {
-  int64_t n = (int64_t)task_base[counts[0]] * stride;
-  if (n > n_max) n = n_max;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    tbuf[i] = v;
+    const int32_t* __restrict__ order, const int32_t* __restrict__ counts,
+    const int32_t* __restrict__ x_n, int32_t x_len, const int32_t* __restrict__ y_n,
+    int32_t y_len, int64_t gram_ny, int32_t lam, int64_t stride, int64_t t_max, uint64_t v) {
+  const int32_t count = counts[0];
+  for (int32_t k = blockIdx.x; k < count; k += gridDim.x) {
+    const int64_t t0 = task_base[k];
+    int64_t t1 = (int64_t)task_base[k + 1] - 1;  // the pair's last task is not filled
+    if (t1 > t_max) t1 = t_max;
+    const int32_t pid = order[k];
+    const int64_t ix = gram_ny ? pid / gram_ny : pid, iy = gram_ny ? pid - ix * gram_ny : pid;
+    const int32_t mx = incs(x_n, x_len, ix), my = incs(y_n, y_len, iy);
+    if (mx <= 0 || my <= 0) continue;  // a single task
+    int64_t n = (int64_t)(mx > my ? mx : my) << lam;
+    if (n > stride) n = stride;
+    for (int64_t t = t0; t < t1; ++t) {
+      uint64_t* __restrict__ p = tbuf + t * stride;
+      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
+    }
+  }
 }
 
 }  // namespace
@@ -171,14 +182,14 @@ hipError_t launch_band_plan(const PairPlanArgs& p, int rows_per_lane, int32_t* t
   return hipGetLastError();
 }
 
-hipError_t launch_fill_task_slots(uint64_t* tbuf, const int32_t* task_base,
-                                  const int32_t* counts, int64_t stride, int64_t n_max,
+hipError_t launch_fill_task_slots(uint64_t* tbuf, const PairPlanArgs& p,
+                                  const int32_t* task_base, int64_t stride, int64_t t_max,
                                   uint64_t v, hipStream_t stream) {
-  if (n_max <= 0) return hipSuccess;
-  int64_t blocks = (n_max + 255) / 256;
-  if (blocks > 16384) blocks = 16384;
+  if (t_max <= 0 || p.npairs <= 0) return hipSuccess;
+  const int32_t blocks = p.npairs < 8192 ? p.npairs : 8192;
   hipLaunchKernelGGL(fill_task_slots_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, tbuf,
-                     task_base, counts, stride, n_max, v);
+                     task_base, p.order, p.counts, p.x_n, p.x_len, p.y_n, p.y_len, p.gram_ny,
+                     p.lam, stride, t_max, v);
   return hipGetLastError();
 }
 

@@ -71,3 +71,39 @@ def test_sixteen_bit_inputs_in_the_sweep():
     assert errs["f32"] <= 1e-5
     assert errs["f16"] <= 2e-3 and errs["bf16"] <= 2e-2
     assert errs["bf16"] > errs["f32"]
+
+
+def rounded_paths(P, precision):
+    """Paths (FP64) whose increments are the 16-bit rounded ones of P."""
+    inc = rounded_increments(P, precision)
+    start = P[..., :1, :].astype(np.float64)
+    return np.concatenate([start, start + np.cumsum(inc, axis=-2)], axis=-2)
+
+
+def mixed_err(got, ref):
+    return np.abs(np.asarray(got, np.float64) - ref) / np.maximum(1.0, np.abs(ref))
+
+
+@pytest.mark.parametrize("precision", ["bf16", "f16"])
+@pytest.mark.parametrize("d", [6, 8, 12, 16])
+def test_sixteen_bit_inputs_match_rounded_paths(precision, d):
+    # the sweep on 16-bit increments is the scheme on the paths with those
+    # increments, to float32 rounding (d a multiple of 4 takes the increments
+    # kernel with 16-byte accesses, d = 6 the one with 4-byte accesses)
+    X = workloads.random_paths(300 + d, 5, 90, d)
+    Y = workloads.random_paths(310 + d, 5, 70, d)
+    got = sk.sigkernel_pair(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), 2,
+                            gram_precision=precision).cpu().numpy()
+    ref = oracle.pairs(rounded_paths(X, precision), rounded_paths(Y, precision), 2)
+    assert mixed_err(got, ref).max() <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["bf16", "f16"])
+def test_sixteen_bit_ragged_match_rounded_paths(precision):
+    xs, ys = workloads.ragged_pairs(n_pairs=24)
+    X = sk.RaggedPaths.from_list(xs, "cuda")
+    Y = sk.RaggedPaths.from_list(ys, "cuda")
+    got = sk.sigkernel_pair(X, Y, 2, gram_precision=precision).cpu().numpy()
+    ref = oracle.pairs([rounded_paths(a, precision) for a in xs],
+                       [rounded_paths(b, precision) for b in ys], 2)
+    assert mixed_err(got, ref).max() <= 1e-5
