@@ -37,7 +37,7 @@ constexpr int kCols = 128; // columns per workgroup (four 32-column tiles)
 using fwd::cell_block;
 using fwd::first_row;
 using fwd::from_prev_lane;
-using fwd::implicit_factor;
+using fwd::implicit_factors;
 using fwd::n_inc;
 using fwd::store_out;
 using fwd::wave_run;
@@ -203,11 +203,14 @@ __global__ __launch_bounds__(256) void coef_sweep_kernel(const SweepArgs a) {
 #pragma unroll
     for (int cc = 0; cc < S; ++cc) up[cc] = from_prev_lane(pub[cc], up[cc]);
     if ((uint32_t)g < (uint32_t)total32) {
-      double gk[CR];
+      double gk[CR], h[CR];
 #pragma unroll
-      for (int c = 0; c < CR; ++c) {
-        const double h = real[c] ? (double)cur[c] : 0.0;
-        gk[c] = IMPL ? implicit_factor(h) : 1.0 + h;
+      for (int c = 0; c < CR; ++c) h[c] = real[c] ? (double)cur[c] : 0.0;
+      if constexpr (IMPL) {
+        implicit_factors<CR>(h, gk);
+      } else {
+#pragma unroll
+        for (int c = 0; c < CR; ++c) gk[c] = 1.0 + h[c];
       }
       double v[R][S];
       float sv[1];

@@ -35,7 +35,7 @@ namespace lift {
 using fwd::cell_block;
 using fwd::first_row;
 using fwd::from_prev_lane;
-using fwd::implicit_factor;
+using fwd::implicit_factors;
 using fwd::load_row;
 using fwd::n_inc;
 using fwd::store_out;
@@ -132,11 +132,14 @@ __global__ __launch_bounds__(256) void lifted_sweep_kernel(const SweepArgs a) {
       if (q < 0) {
         q = 0;
       } else {
-        double gk[CR];
+        double gk[CR], h[CR];
 #pragma unroll
-        for (int c = 0; c < CR; ++c) {
-          const double h = (dn[c] - dprev[c]) * scale;
-          gk[c] = a.implicit ? implicit_factor(h) : 1.0 + h;
+        for (int c = 0; c < CR; ++c) h[c] = (dn[c] - dprev[c]) * scale;
+        if (a.implicit) {
+          implicit_factors<CR>(h, gk);
+        } else {
+#pragma unroll
+          for (int c = 0; c < CR; ++c) gk[c] = 1.0 + h[c];
         }
         double v[R][S];
         float sv[1];

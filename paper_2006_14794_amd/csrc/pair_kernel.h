@@ -128,11 +128,14 @@ __global__ __launch_bounds__(256) void pair_kernel(const PairArgs a) {
 
         if ((uint32_t)g < (uint32_t)n) {
           double gk[CR];
+          if (a.implicit) {
+            double h[CR];
 #pragma unroll
-          for (int c = 0; c < CR; ++c) {
-            const double h = (double)h32[c] * a.scale;  // exact: scale is a power of two
-            gk[c] = a.implicit ? fwd::implicit_factor(h)
-                               : __builtin_fma((double)h32[c], a.scale, 1.0);
+            for (int c = 0; c < CR; ++c) h[c] = (double)h32[c] * a.scale;  // exact: 2^-k
+            fwd::implicit_factors<CR>(h, gk);
+          } else {
+#pragma unroll
+            for (int c = 0; c < CR; ++c) gk[c] = __builtin_fma((double)h32[c], a.scale, 1.0);
           }
           double v[R][S];
 #pragma unroll
@@ -323,11 +326,14 @@ __device__ __forceinline__ void band_sweep(const PairArgs& a,
 
     if ((uint32_t)g < (uint32_t)n) {
       double gk[CR];
+      if (a.implicit) {
+        double h[CR];
 #pragma unroll
-      for (int c = 0; c < CR; ++c) {
-        const double h = (double)h32[c] * a.scale;  // exact: scale is a power of two
-        gk[c] = a.implicit ? fwd::implicit_factor(h)
-                           : __builtin_fma((double)h32[c], a.scale, 1.0);
+        for (int c = 0; c < CR; ++c) h[c] = (double)h32[c] * a.scale;  // exact: 2^-k
+        fwd::implicit_factors<CR>(h, gk);
+      } else {
+#pragma unroll
+        for (int c = 0; c < CR; ++c) gk[c] = __builtin_fma((double)h32[c], a.scale, 1.0);
       }
       double v[RT][S];
       float sv[1];

@@ -50,19 +50,50 @@ __device__ __forceinline__ double from_prev_lane(double v, double keep) {
                                           (unsigned long long)(unsigned)lo));
 }
 
-// Cell factor of the implicit scheme, (2 + h) / (2 - h): the hardware
-// reciprocal of 2 - h refined by two Newton-Raphson steps (each at least
-// squares the relative error), then one product -- within a few ulp, at about
-// half the cost of an IEEE division.  h = 2 gives inf or NaN, as the division
-// would (the scheme has no solution there).
-__device__ __forceinline__ double implicit_factor(double h) {
-  const double den = 2.0 - h;
+// 1 / den: the hardware reciprocal refined by two Newton-Raphson steps (each
+// at least squares the relative error), within a few ulp at about half the
+// cost of an IEEE division; 0 gives NaN.
+__device__ __forceinline__ double refined_reciprocal(double den) {
   double r = __builtin_amdgcn_rcp(den);
   double e = __builtin_fma(-den, r, 1.0);
   r = __builtin_fma(r, e, r);
   e = __builtin_fma(-den, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  return (2.0 + h) * r;
+  return __builtin_fma(r, e, r);
+}
+
+// Cell factors of the implicit scheme, g = (2 + h) / (2 - h) = 4 / (2 - h) - 1,
+// for a lane's CR coarse rows.  The reciprocals of each group of up to four
+// d = 2 - h come from one reciprocal of their product and back-multiplication
+// (batch inversion: with q_i = d_0 ... d_i, 1/d_i = q_{i-1} / q_i), which
+// replaces three quarter-rate reciprocals and their Newton steps by six
+// products.  Each reciprocal is within a few ulp; g is formed with one fused
+// multiply-add.  For h that are floats times a power of two, |d| is 0 or at
+// least 2^-23, so the product of four stays inside the double range; h = 2
+// gives NaN factors for its group (the scheme has no solution there).
+template <int CR>
+__device__ __forceinline__ void implicit_factors(const double (&h)[CR], double (&g)[CR]) {
+#pragma unroll
+  for (int c0 = 0; c0 < CR; c0 += 4) {
+    constexpr int kGroup = 4;
+    const int n = CR - c0 < kGroup ? CR - c0 : kGroup;
+    double d[kGroup], q[kGroup];
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) {
+      if (i < n) {
+        d[i] = 2.0 - h[c0 + i];
+        q[i] = i ? q[i - 1] * d[i] : d[i];
+      }
+    }
+    double r = refined_reciprocal(q[n - 1]);  // 1 / q_{n-1}
+#pragma unroll
+    for (int i = kGroup - 1; i >= 1; --i) {
+      if (i < n) {
+        g[c0 + i] = __builtin_fma(4.0, r * q[i - 1], -1.0);  // 1/d_i = q_{i-1} / q_i
+        r *= d[i];                                          // 1 / q_{i-1}
+      }
+    }
+    g[c0] = __builtin_fma(4.0, r, -1.0);
+  }
 }
 
 template <int DP>
@@ -266,10 +297,14 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
 
     if ((uint32_t)g < (uint32_t)total32) {
       double gk[CR];
+      if constexpr (IMPL) {
+        double h[CR];
 #pragma unroll
-      for (int c = 0; c < CR; ++c) {
-        const double h = (double)h32[c];
-        gk[c] = IMPL ? implicit_factor(h) : 1.0 + h;
+        for (int c = 0; c < CR; ++c) h[c] = (double)h32[c];
+        implicit_factors<CR>(h, gk);
+      } else {
+#pragma unroll
+        for (int c = 0; c < CR; ++c) gk[c] = 1.0 + (double)h32[c];
       }
       double v[R][S];
       float sv[STORE ? R * S : 1];
