@@ -262,18 +262,29 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const ConvArgs a) {
 }
 
 // ------------------------------------------------------ fused inference --
-// One workgroup (8 waves) per pair: the feature map, layer 1's output and the
-// current layer's weights stay in LDS; layers 2-4 reuse the feature map's
-// space; only the two outputs leave the chip.
+// Persistent workgroups of 8 waves, one pair at a time: the feature map,
+// layer 1's output and the current layer's weights stay in LDS; layer 2's
+// output reuses the feature map's space and layers 3-4 that of layer 1; only
+// the two outputs leave the chip.  While a pair is evaluated, waves 4-7 hold
+// the next pair's feature map in registers (loaded at the start, written to
+// LDS once layer 3 has read the feature map's space), and waves 0-3 stage the
+// weights: a wave's global loads complete in order, so the waves that wait on
+// weight loads must not be the ones with the feature loads in flight.
 constexpr int kNetThreads = 512;
-constexpr int kLdsF = kFeatFloats;              // feature map, later layers 2-4
-constexpr int kLdsA1 = 32 * 32 * kCout;         // layer 1 output
+constexpr int kLdsF = kFeatFloats;              // feature map, later layer 2
+constexpr int kLdsA1 = 32 * 32 * kCout;         // layer 1 output, later layers 3-4
 constexpr int kLdsW = kCout * 9 * 32;           // one layer's weights
+constexpr int kStageThreads = 256;              // waves 0-3
+constexpr int kFeat16 = kFeatFloats / 8;        // 16-byte chunks of a feature map
+constexpr int kPre = kFeat16 / (kNetThreads - kStageThreads);  // per thread of waves 4-7
+static_assert(kPre * (kNetThreads - kStageThreads) == kFeat16, "feature map split");
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // stays in registers
 
 template <int CIN>
 __device__ __forceinline__ void stage_weights(bf16* W, const bf16* src, int tid) {
   constexpr int N16 = kCout * 9 * CIN / 8;  // 16-byte chunks
-  for (int i = tid; i < N16; i += kNetThreads)
+  if (tid >= kStageThreads) return;
+  for (int i = tid; i < N16; i += kStageThreads)
     reinterpret_cast<uint4*>(W)[i] = reinterpret_cast<const uint4*>(src)[i];
 }
 
@@ -282,65 +293,88 @@ __global__ __launch_bounds__(kNetThreads) void net_fused_kernel(const NetArgs a)
   bf16* F = lds;
   bf16* A1 = lds + kLdsF;
   bf16* W = lds + kLdsF + kLdsA1;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int64_t pn = blockIdx.x;
-  {
-    const uint4* src = reinterpret_cast<const uint4*>(a.feats + pn * (int64_t)kFeatFloats);
-    for (int i = tid; i < kFeatFloats / 8; i += kNetThreads) reinterpret_cast<uint4*>(F)[i] = src[i];
-  }
-  stage_weights<8>(W, a.wb + param_offset(0), tid);
-  __syncthreads();
-  for (int t = wid; t < 32; t += 8) {  // layer 1: 64 x 64 x 8 -> 32 x 32 x 32
-    f32x16 acc = {};
-    conv_tile<8, 64>(F, W, t, lane, acc);
-    store_tile<32 * 32>(acc, a.params[param_offset(0) + kCout * 9 * 8 + (lane & 31)], A1, t, lane);
-  }
-  __syncthreads();
-  stage_weights<32>(W, a.wb + param_offset(1), tid);
-  __syncthreads();
   bf16* A2 = F;                 // 16 x 16 x 32
-  bf16* A3 = F + 16 * 16 * 32;  // 8 x 8 x 32
-  bf16* A4 = A3 + 8 * 8 * 32;   // 4 x 4 x 32
-  {
-    f32x16 acc = {};
-    conv_tile<32, 32>(A1, W, wid, lane, acc);
-    store_tile<16 * 16>(acc, a.params[param_offset(1) + kCout * 9 * 32 + (lane & 31)], A2, wid,
-                        lane);
-  }
-  __syncthreads();
-  stage_weights<32>(W, a.wb + param_offset(2), tid);
-  __syncthreads();
-  if (wid < 2) {
-    f32x16 acc = {};
-    conv_tile<32, 16>(A2, W, wid, lane, acc);
-    store_tile<8 * 8>(acc, a.params[param_offset(2) + kCout * 9 * 32 + (lane & 31)], A3, wid, lane);
-  }
-  __syncthreads();
-  stage_weights<32>(W, a.wb + param_offset(3), tid);
-  __syncthreads();
-  if (wid == 0) {
-    f32x16 acc = {};
-    conv_tile<32, 8>(A3, W, 0, lane, acc);
-    store_tile<4 * 4>(acc, a.params[param_offset(3) + kCout * 9 * 32 + (lane & 31)], A4, 0, lane);
-  }
-  __syncthreads();
-  if (wid == 0) {  // head, in the order of head_fwd_kernel
-    const float* __restrict__ wh = a.params + kHeadOffset;
-    float s0 = 0.0f, s1 = 0.0f;
-    for (int k = lane; k < kHeadIn; k += 64) {
-      const float x = (float)A4[k];
-      s0 = __builtin_fmaf(x, wh[k], s0);
-      s1 = __builtin_fmaf(x, wh[kHeadIn + k], s1);
-    }
+  bf16* A3 = A1;                // 8 x 8 x 32
+  bf16* A4 = A1 + 8 * 8 * 32;   // 4 x 4 x 32
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  // the biases of the four layers (the same for every pair)
+  float bias[4];
+  bias[0] = a.params[param_offset(0) + kCout * 9 * 8 + (lane & 31)];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      s0 += __shfl_xor(s0, off, 64);
-      s1 += __shfl_xor(s1, off, 64);
+  for (int l = 1; l < 4; ++l) bias[l] = a.params[param_offset(l) + kCout * 9 * 32 + (lane & 31)];
+  if ((int64_t)blockIdx.x < a.n) {
+    const uint4* src = reinterpret_cast<const uint4*>(a.feats + blockIdx.x * (int64_t)kFeatFloats);
+    for (int i = tid; i < kFeat16; i += kNetThreads) reinterpret_cast<uint4*>(F)[i] = src[i];
+  }
+  for (int64_t pn = blockIdx.x; pn < a.n; pn += gridDim.x) {
+    const int64_t nx = pn + gridDim.x;
+    const bool pre = wid >= 4 && nx < a.n;
+    u32x4 next[kPre];
+    if (pre) {
+      const u32x4* src = reinterpret_cast<const u32x4*>(a.feats + nx * (int64_t)kFeatFloats);
+#pragma unroll
+      for (int j = 0; j < kPre; ++j)
+        next[j] = src[(tid - kStageThreads) + j * (kNetThreads - kStageThreads)];
     }
-    if (lane == 0) {
+    stage_weights<8>(W, a.wb + param_offset(0), tid);
+    __syncthreads();
+    for (int t = wid; t < 32; t += 8) {  // layer 1: 64 x 64 x 8 -> 32 x 32 x 32
+      f32x16 acc = {};
+      conv_tile<8, 64>(F, W, t, lane, acc);
+      store_tile<32 * 32>(acc, bias[0], A1, t, lane);
+    }
+    __syncthreads();
+    stage_weights<32>(W, a.wb + param_offset(1), tid);
+    __syncthreads();
+    {
+      f32x16 acc = {};
+      conv_tile<32, 32>(A1, W, wid, lane, acc);
+      store_tile<16 * 16>(acc, bias[1], A2, wid, lane);
+    }
+    __syncthreads();
+    stage_weights<32>(W, a.wb + param_offset(2), tid);
+    __syncthreads();
+    if (wid < 2) {
+      f32x16 acc = {};
+      conv_tile<32, 16>(A2, W, wid, lane, acc);
+      store_tile<8 * 8>(acc, bias[2], A3, wid, lane);
+    }
+    __syncthreads();
+    // the feature map's space is free: the next pair's map goes in
+    if (pre) {
+#pragma unroll
+      for (int j = 0; j < kPre; ++j)
+        reinterpret_cast<u32x4*>(F)[(tid - kStageThreads) + j * (kNetThreads - kStageThreads)] =
+            next[j];
+    }
+    stage_weights<32>(W, a.wb + param_offset(3), tid);
+    __syncthreads();
+    if (wid == 0) {
+      f32x16 acc = {};
+      conv_tile<32, 8>(A3, W, 0, lane, acc);
+      store_tile<4 * 4>(acc, bias[3], A4, 0, lane);
+    }
+    __syncthreads();
+    if (wid == 0) {  // head, in the order of head_fwd_kernel
+      const float* __restrict__ wh = a.params + kHeadOffset;
+      float s0 = 0.0f, s1 = 0.0f;
+      for (int k = lane; k < kHeadIn; k += 64) {
+        const float x = (float)A4[k];
+        s0 = __builtin_fmaf(x, wh[k], s0);
+        s1 = __builtin_fmaf(x, wh[kHeadIn + k], s1);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        s0 += __shfl_xor(s0, off, 64);
+        s1 += __shfl_xor(s1, off, 64);
+      }
+      // every lane of the wave holds the same sums (the butterfly adds the
+      // same two operands in every lane) and stores them
       a.y[2 * pn] = s0 + wh[2 * kHeadIn];
       a.y[2 * pn + 1] = s1 + wh[2 * kHeadIn + 1];
     }
+    // the next pair's layer 1 overwrites layers 3-4 only after the barrier
+    // that follows its weight staging, which wave 0 reaches after the head
   }
 }
 
@@ -783,7 +817,13 @@ hipError_t launch_channel_stats(const void* x, bool x_bf16, const float* sub, in
 
 hipError_t launch_net_fused(const NetArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(net_fused_kernel, dim3((unsigned)a.n), dim3(kNetThreads), 0, s, a);
+  // one persistent workgroup per compute unit (the LDS holds one)
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return hipErrorInvalidDevice;
+  const int64_t blocks = a.n < (int64_t)cus ? a.n : (int64_t)(cus > 0 ? cus : 1);
+  hipLaunchKernelGGL(net_fused_kernel, dim3((unsigned)blocks), dim3(kNetThreads), 0, s, a);
   return hipGetLastError();
 }
 

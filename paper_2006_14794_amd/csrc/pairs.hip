@@ -33,8 +33,12 @@ __global__ __launch_bounds__(1024) void pair_plan_kernel(
     cmax[threadIdx.x] = 0;
   }
   __syncthreads();
+  // rows per lane are powers of two: bands by a shift (no 64-bit division)
+  const int sh_lo = 6 + (rows_lo > 0 ? __builtin_ctz((unsigned)rows_lo) : 0);
+  const int sh_hi = 6 + __builtin_ctz((unsigned)(rows_hi > 0 ? rows_hi : 1));
   auto classify = [&](int32_t k, unsigned long long& cost) -> int {
-    const int64_t ix = gram_ny ? k / gram_ny : k, iy = gram_ny ? k - ix * gram_ny : k;
+    const uint32_t ny = (uint32_t)gram_ny;  // npairs < 2^31
+    const int64_t ix = ny ? (uint32_t)k / ny : k, iy = ny ? k - ix * (int64_t)ny : k;
     const int32_t mx = incs(x_n, x_len, ix), my = incs(y_n, y_len, iy);
     if (mx <= 0 || my <= 0) {
       cost = 0;
@@ -45,33 +49,84 @@ __global__ __launch_bounds__(1024) void pair_plan_kernel(
     const int64_t mn = mx < my ? mx : my, mxn = mx < my ? my : mx;
     const int64_t M = mn << lam;
     const int cls = M <= 64 * (int64_t)rows_lo ? 0 : 1;
-    const int64_t band_rows = 64 * (int64_t)(cls ? rows_hi : rows_lo);
-    const int64_t bands = (M + band_rows - 1) / band_rows;
+    const int sh = cls ? sh_hi : sh_lo;
+    const int64_t bands = (M + (int64_t(1) << sh) - 1) >> sh;
     cost = (unsigned long long)(bands * (mxn + 63));
     if (cost > (1ull << 45) - 1) cost = (1ull << 45) - 1;
     return cls;
   };
-  // bucket of a pair: long class first, each class by decreasing cost
-  auto bucket = [&](int cls, unsigned long long cost) -> int {
-    const unsigned long long q = cost * kBuckets / (cmax[cls] + 1);  // 0 .. kBuckets-1
-    return (cls ? 0 : kBuckets) + (kBuckets - 1 - (int)q);
-  };
-  for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x) {
+  // a batch of equal lengths: every pair has the same cost and class, so the
+  // identity order is already sorted
+  if (!x_n && !y_n) {
     unsigned long long cost;
-    const int cls = classify(k, cost);
-    atomicAdd(&cnt[cls], 1);
-    atomicMax(&cmax[cls], cost);
+    const int cls = npairs > 0 ? classify(0, cost) : 1;
+    for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x) order[k] = k;
+    if (threadIdx.x == 0) {
+      counts[0] = cls ? npairs : 0;
+      counts[1] = cls ? 0 : npairs;
+      counters[0] = 0;
+      counters[1] = 0;
+    }
+    return;
+  }
+  // bucket of a pair: long class first, each class by decreasing cost; the
+  // cost ranges are the leading bits of the cost below the class maximum's
+  // next power of two (a shift, no 64-bit division)
+  auto bucket = [&](int cls, unsigned long long cost) -> int {
+    const int len = 64 - __clzll((long long)cmax[cls]);  // bits of the maximum
+    const int q = len > 10 ? (int)(cost >> (len - 10)) : (int)(cost << (10 - len));
+    return (cls ? 0 : kBuckets) + (kBuckets - 1 - q);  // q in 0 .. kBuckets-1
+  };
+  // Every pass runs all lanes (k past npairs: not counted) and takes one LDS
+  // atomic per wave where the wave's pairs agree (a batch of equal lengths
+  // puts every pair in one bucket), one per lane otherwise.
+  const int lane = threadIdx.x & 63;
+  auto wave_add = [&](int32_t* ctr, bool ok, int b) -> int32_t {  // ctr[b] += 1 per ok lane
+    const unsigned long long act = __ballot(ok);
+    if (act == 0) return 0;
+    const int first = __ffsll(act) - 1;
+    const int b0 = __shfl(b, first, 64);
+    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0));
+    if (__ballot(ok && b == b0) == act) {
+      int32_t base = 0;
+      if (lane == first) base = atomicAdd(&ctr[b0], __popcll(act));
+      return __shfl(base, first, 64) + rank;
+    }
+    return ok ? atomicAdd(&ctr[b], 1) : 0;
+  };
+  for (int32_t base = 0; base < npairs; base += blockDim.x) {
+    const int32_t k = base + (int32_t)threadIdx.x;
+    const bool ok = k < npairs;
+    unsigned long long cost = 0;
+    const int cls = ok ? classify(k, cost) : 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const unsigned long long in = __ballot(ok && cls == c);
+      unsigned long long m = (ok && cls == c) ? cost : 0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+      }
+      if (lane == 0 && in != 0) {
+        atomicAdd(&cnt[c], __popcll(in));
+        atomicMax(&cmax[c], m);
+      }
+    }
   }
   __syncthreads();
-  for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x) {
-    unsigned long long cost;
-    const int cls = classify(k, cost);
-    atomicAdd(&hist[bucket(cls, cost)], 1);
+  for (int32_t base = 0; base < npairs; base += blockDim.x) {
+    const int32_t k = base + (int32_t)threadIdx.x;
+    const bool ok = k < npairs;
+    unsigned long long cost = 0;
+    const int cls = ok ? classify(k, cost) : 0;
+    wave_add(hist, ok, ok ? bucket(cls, cost) : 0);
   }
   __syncthreads();
   // exclusive scan of the 2 kBuckets counts: two per thread, then across waves
   {
-    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int t = threadIdx.x, wid = t >> 6;
     const int32_t a0 = hist[2 * t], a1 = hist[2 * t + 1];
     int32_t v = a0 + a1;
 #pragma unroll
@@ -88,10 +143,13 @@ __global__ __launch_bounds__(1024) void pair_plan_kernel(
     hist[2 * t + 1] = start + a0;
   }
   __syncthreads();
-  for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x) {
-    unsigned long long cost;
-    const int cls = classify(k, cost);
-    order[atomicAdd(&hist[bucket(cls, cost)], 1)] = k;
+  for (int32_t base = 0; base < npairs; base += blockDim.x) {
+    const int32_t k = base + (int32_t)threadIdx.x;
+    const bool ok = k < npairs;
+    unsigned long long cost = 0;
+    const int cls = ok ? classify(k, cost) : 0;
+    const int32_t pos = wave_add(hist, ok, ok ? bucket(cls, cost) : 0);
+    if (ok) order[pos] = k;
   }
   __syncthreads();
   if (threadIdx.x == 0) {

@@ -227,10 +227,12 @@ def test_predict_without_fallback_matches_oracle_network():
     assert np.allclose(err.cpu().numpy(), e_ref, rtol=5e-3)
 
 
-def test_fused_predict_equals_layerwise_forward():
+@pytest.mark.parametrize("n", [70, 600])
+def test_fused_predict_equals_layerwise_forward(n):
     # the on-chip network of predict and the layer-by-layer training forward
-    # run the same instructions: with target_norm = (0, 1), k_hat - k0 is y0
-    n = 70
+    # run the same instructions: with target_norm = (0, 1), k_hat - k0 is y0.
+    # 600 pairs: the persistent workgroups (one per compute unit) take
+    # several pairs each, the later ones from their prefetch registers
     X, Y = workloads.corrector_pairs(15, n, n_points=256, dim=8)
     Xc, Yc = cuda(X), cuda(Y)
     theta = corr.init_params(16)
