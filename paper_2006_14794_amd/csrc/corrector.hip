@@ -49,9 +49,15 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
     rs[c] = a.norm ? a.norm[kFeatChannels + c] : 1.0f;
   }
   // block (P, Q) of this lane's strip: moments f[0..5] plus coordinates,
-  // normalised in float32 and stored as eight bf16 (16 bytes)
+  // normalised in float32 and stored as eight bf16 (16 bytes).  The
+  // coordinates P / 63 and Q / 63 (P, Q in 0 .. 63) are the correctly rounded
+  // float quotients, formed as one double product with 1/63 rounded once to
+  // float: the binary expansion of a multiple of 1/63 repeats 000001, so it is
+  // never within the product's error of a float rounding midpoint (checked
+  // for all 64 values against the float division).
+  auto coord = [](int P) { return (float)((double)P * (1.0 / 63.0)); };
   auto put = [&](int P, int Q, const float (&f)[6]) {
-    const float v[kFeatChannels] = {f[0], f[1], f[2], f[3], f[4], f[5], P / 63.0f, Q / 63.0f};
+    const float v[kFeatChannels] = {f[0], f[1], f[2], f[3], f[4], f[5], coord(P), coord(Q)};
     bf16x8 o;
 #pragma unroll
     for (int c = 0; c < kFeatChannels; ++c) o[c] = (bf16)((v[c] - mu[c]) * rs[c]);
