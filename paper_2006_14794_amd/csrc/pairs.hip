@@ -60,7 +60,7 @@ __global__ __launch_bounds__(1024) void pair_plan_kernel(
   if (!x_n && !y_n) {
     unsigned long long cost;
     const int cls = npairs > 0 ? classify(0, cost) : 1;
-    for (int32_t k = threadIdx.x; k < npairs; k += blockDim.x) order[k] = k;
+    for (int64_t k = threadIdx.x; k < npairs; k += blockDim.x) order[k] = (int32_t)k;
     if (threadIdx.x == 0) {
       counts[0] = cls ? npairs : 0;
       counts[1] = cls ? 0 : npairs;
@@ -95,9 +95,9 @@ __global__ __launch_bounds__(1024) void pair_plan_kernel(
     }
     return ok ? atomicAdd(&ctr[b], 1) : 0;
   };
-  for (int32_t base = 0; base < npairs; base += blockDim.x) {
-    const int32_t k = base + (int32_t)threadIdx.x;
-    const bool ok = k < npairs;
+  for (int64_t base = 0; base < npairs; base += blockDim.x) {  // 64-bit: npairs < 2^31
+    const bool ok = base + threadIdx.x < npairs;
+    const int32_t k = ok ? (int32_t)(base + threadIdx.x) : 0;
     unsigned long long cost = 0;
     const int cls = ok ? classify(k, cost) : 0;
 #pragma unroll
@@ -116,9 +116,9 @@ __global__ __launch_bounds__(1024) void pair_plan_kernel(
     }
   }
   __syncthreads();
-  for (int32_t base = 0; base < npairs; base += blockDim.x) {
-    const int32_t k = base + (int32_t)threadIdx.x;
-    const bool ok = k < npairs;
+  for (int64_t base = 0; base < npairs; base += blockDim.x) {  // 64-bit: npairs < 2^31
+    const bool ok = base + threadIdx.x < npairs;
+    const int32_t k = ok ? (int32_t)(base + threadIdx.x) : 0;
     unsigned long long cost = 0;
     const int cls = ok ? classify(k, cost) : 0;
     wave_add(hist, ok, ok ? bucket(cls, cost) : 0);
@@ -143,9 +143,9 @@ __global__ __launch_bounds__(1024) void pair_plan_kernel(
     hist[2 * t + 1] = start + a0;
   }
   __syncthreads();
-  for (int32_t base = 0; base < npairs; base += blockDim.x) {
-    const int32_t k = base + (int32_t)threadIdx.x;
-    const bool ok = k < npairs;
+  for (int64_t base = 0; base < npairs; base += blockDim.x) {  // 64-bit: npairs < 2^31
+    const bool ok = base + threadIdx.x < npairs;
+    const int32_t k = ok ? (int32_t)(base + threadIdx.x) : 0;
     unsigned long long cost = 0;
     const int cls = ok ? classify(k, cost) : 0;
     const int32_t pos = wave_add(hist, ok, ok ? bucket(cls, cost) : 0);
@@ -171,8 +171,8 @@ __global__ __launch_bounds__(1024) void band_plan_kernel(
   const int32_t count = counts[0];
   // 1024 pairs at a time, carrying the running total between chunks
   int32_t carry = 0;
-  for (int32_t base = 0; base < count; base += 1024) {
-    const int32_t k = base + (int32_t)threadIdx.x;
+  for (int64_t base = 0; base < count; base += 1024) {  // 64-bit: count < 2^31
+    const int32_t k = base + threadIdx.x < count ? (int32_t)(base + threadIdx.x) : count;
     int32_t nb = 0;
     if (k < count) {
       const int32_t pid = order[k];
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void fill_task_slots_kernel(
     const int32_t* __restrict__ x_n, int32_t x_len, const int32_t* __restrict__ y_n,
     int32_t y_len, int64_t gram_ny, int32_t lam, int64_t stride, int64_t t_max, uint64_t v) {
   const int32_t count = counts[0];
-  for (int32_t k = blockIdx.x; k < count; k += gridDim.x) {
+  for (int64_t k = blockIdx.x; k < count; k += gridDim.x) {
     const int64_t t0 = task_base[k];
     int64_t t1 = (int64_t)task_base[k + 1] - 1;  // the pair's last task is not filled
     if (t1 > t_max) t1 = t_max;
