@@ -96,6 +96,8 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
   double up_last = 1.0;                // K[p0][q]: the upper-left node of row 0
   float up_last_f = 1.0f;
   float f[6] = {0, 0, 0, 0, 0, 0};
+  float hf[6] = {0, 0, 0, 0, 0, 0};  // the last full block this lane ended
+  int hq = -1;                       // its block column, -1: none pending
   const float* __restrict__ ybase = a.incy + pair * (int64_t)n * DP;
   auto fetch = [&](int q, float (&row)[DP]) {
     if (q < n) {
@@ -154,20 +156,38 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
       uf[r] = nvf[r];
     }
     pub = nv[3];
-    if ((q & 3) == 3 || q == n - 1) {
-      put(lane, q >> 2, f);
+    // a full block ends at column q = 4Q + 3: its moments move to the held
+    // registers (selects, no branch: a quarter of the lanes end a block at
+    // every step, as the lanes are one column apart)
+    const bool done = (q & 3) == 3;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) f[k] = 0.0f;
+    for (int k = 0; k < 6; ++k) {
+      hf[k] = done ? f[k] : hf[k];
+      f[k] = done ? 0.0f : f[k];
     }
-    if (q == n - 1 && lane == (m - 1) >> 2) a.k0[pair] = (float)nv[(m - 1) & 3];
+    hq = done ? q >> 2 : hq;
+  };
+  // the held blocks are written by the whole wave every fourth step: a lane
+  // ends at most one full block per four steps, so none is overwritten first
+  auto flush = [&]() {
+    if (hq >= 0) put(lane, hq, hf);
+    hq = -1;
   };
   float dyA[DP], dyB[DP];
   fetch(0, dyA);
   const int nsteps = n + 63;
-  for (int t = 0; t < nsteps; t += 2) {
+  for (int t = 0; t < nsteps; t += 4) {
     step(t, dyA, dyB);
-    if (t + 1 < nsteps) step(t + 1, dyB, dyA);
+    step(t + 1, dyB, dyA);
+    step(t + 2, dyA, dyB);
+    step(t + 3, dyB, dyA);
+    flush();
   }
+  flush();
+  // the last block, when n is not a multiple of 4, ends partial
+  if (n & 3) put(lane, n >> 2, f);
+  // k = K[m - 1][n - 1]: the last node of row m - 1, held by its lane
+  if (lane == (m - 1) >> 2) a.k0[pair] = (float)u[(m - 1) & 3];
   for (int Q = (n + 3) >> 2; Q < kBlocks; ++Q) put(lane, Q, zero6);
 }
 
