@@ -1033,7 +1033,7 @@ sk_status sigkernel_increment_gram(const sk_paths* X, const sk_paths* Y, int32_t
   const int64_t pairs = gram ? X->n_paths * Y->n_paths : X->n_paths;
   if (pairs == 0 || X->len < 2 || Y->len < 2) return SK_OK;
   if (!G0 || !X->points || !Y->points) return SK_ERR_NULL;
-  if ((int64_t)((X->len + 30) / 32) > 65535 || X->dim > 16) return SK_ERR_UNSUPPORTED;
+  if (X->dim > 16) return SK_ERR_UNSUPPORTED;  // the kernel stages at most 16 channels
   sk::GramArgs a{};
   a.x = X->points;
   a.y = Y->points;
