@@ -49,6 +49,23 @@ def test_fixed_penalty_iterates_and_losses(fbm_gram):
     assert np.abs(loss.cpu().numpy() - ref_loss).max() <= 1e-10 * np.abs(ref_loss).max()
 
 
+@pytest.mark.parametrize("n", [1, 32, 33, 64])
+def test_one_wave_sizes(n):
+    # up to 64 atoms one wave holds K in registers (32 or 64 columns, zero
+    # beyond n): iterates, losses and the power-iteration step of a fixed
+    # penalty against the oracle
+    K = spd(40 + n, n, cond=8.0)
+    K64 = K.astype(np.float64)
+    alpha = np.full(n, np.float32(1.0 / n)).astype(np.float64)
+    lam = 1e-3
+    beta, loss, used = sk.reduced_measure(torch.from_numpy(K).cuda(), lam, 200)
+    lip = rm.lipschitz(K64)
+    assert 0.9 / lip <= used.item() <= 1.0 / lip
+    ref, ref_loss = rm.ista(K64, alpha, lam, 200, step=used.item())
+    assert np.abs(beta.cpu().numpy() - ref).max() <= 1e-10
+    assert np.abs(loss.cpu().numpy() - ref_loss).max() <= 1e-10 * np.abs(ref_loss).max()
+
+
 def test_automatic_step_reaches_the_minimiser():
     K = spd(11, 200)
     K64 = K.astype(np.float64)
