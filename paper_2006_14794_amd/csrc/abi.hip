@@ -126,6 +126,10 @@ constexpr int64_t kPairSlots = 4096;
 // Pipelined bands (pair_band_kernel) for batches whose grids need several
 // bands, when every band task's slot buffer fits this budget.
 constexpr size_t kPipeCapBytes = size_t(1) << 30;
+// SIMDs of the target (256 compute units of 4): the band-height model's
+// notion of a full chip (a constant, so that workspace sizes do not depend
+// on the device queried)
+constexpr int64_t kSimds = 1024;
 
 struct PairLayout {
   int rows_lo, rows_hi;
@@ -152,6 +156,39 @@ PairLayout pair_layout(const sk_paths* X0, const sk_paths* Y0, int32_t lam0, boo
     if (sk::sweep_fn(sk::kKernelPair, lam, R, d)) rmax = R;
   int rhi = 1;
   while (rhi < rmax && 64 * (int64_t)rhi < rows) rhi *= 2;
+  // Few long pairs of equal length: lower bands (fewer rows per lane) keep
+  // more SIMDs busy and make each step cheaper, at the price of more
+  // hand-overs, each band lagging the one above by about a pipeline fill plus
+  // a staging chunk (80 steps).  Modelled time of a pair: (columns + 63 +
+  // (bands - 1) 80) steps of cost R + 20, times the waves per SIMD beyond one.
+  // The 20 rows stand for the part of a step that does not shrink with R: a
+  // wave alone on its SIMD waits on latencies (DPP hand-off, loads, the
+  // cells' dependency chain) more than it issues.  Fitted to five pairs of
+  // 2000 points at order 4 (8.05, 6.98, 7.60, 10.77 ms at R = 32, 16, 8, 4).
+  if (rmax && rhi == rmax && !X0->offsets && !Y0->offsets && rows > 64 * (int64_t)rmax) {
+    const int64_t cols = (X->len > Y->len ? X->len : Y->len) - 1;
+    auto cost = [&](int R) {
+      const int64_t nb = (rows + 64 * (int64_t)R - 1) / (64 * (int64_t)R);
+      const double share = (double)(nb * npairs) / kSimds;
+      return (double)(cols + 63 + (nb - 1) * 80) * (R + 20) * (share > 1.0 ? share : 1.0);
+    };
+    // a height whose band tasks' slot buffers exceed the budget would lose
+    // the pipeline: not a candidate
+    const int64_t stride = (X->len > Y->len ? X->len : Y->len) + 2 * sk::kStreamPad;
+    auto fits = [&](int R) {
+      const int64_t nb = (rows + 64 * (int64_t)R - 1) / (64 * (int64_t)R);
+      return (size_t)(nb * npairs) * (size_t)(stride << lam) * sizeof(double) <= kPipeCapBytes;
+    };
+    double best = cost(rmax);
+    for (int R = rmax / 2; R >= 1; R /= 2) {
+      if (!sk::sweep_fn(sk::kKernelPairBandFull, lam, R, d) || !fits(R)) continue;
+      const double c = cost(R);
+      if (c < best) {
+        best = c;
+        rhi = R;
+      }
+    }
+  }
   L.rows_hi = rmax ? rhi : 0;
   L.rows_lo = rhi > 1 ? rhi / 2 : rhi;
   // wave slots: a whole number of 4-wave workgroups
@@ -401,8 +438,9 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam0, float* o
     b.tstride = PL.band_stride;
     // a batch of equal lengths has one top band for all its pairs: when it
     // needs all R rows per lane, the kernel with bands of one height runs
-    bool fit_top = true;
-    if (!X->offsets && !Y->offsets) {
+    // (the fitted kernel exists at the largest fitting height only)
+    bool fit_top = sk::sweep_fn(sk::kKernelPairBand, lam, PL.rows_hi, d) != nullptr;
+    if (fit_top && !X->offsets && !Y->offsets) {
       const int64_t band_rows = 64 * (int64_t)PL.rows_hi;
       const int64_t M = (int64_t)((Xr.len < Yr.len ? Xr.len : Yr.len) - 1) << lam;
       const int64_t top_rows = M - (M - 1) / band_rows * band_rows;

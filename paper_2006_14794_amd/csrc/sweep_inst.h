@@ -53,11 +53,14 @@ struct Pair {
   }
 };
 #elif SK_KIND == 6 || SK_KIND == 7
+// fitted top band (6): ragged batches, at the largest fitting height only;
+// one height (7): batches of equal lengths, at every height (few long pairs
+// run lower bands, see pair_layout)
 struct PairBand {
   using Fn = void*;
   template <int R, int LAM, int D>
   static Fn get() {
-    if constexpr (sweep_fits(R, LAM, D) && R == max_fitting_rows(LAM, D))
+    if constexpr (sweep_fits(R, LAM, D) && (SK_KIND == 7 || R == max_fitting_rows(LAM, D)))
       return reinterpret_cast<void*>(&pairk::pair_band_kernel<R, LAM, D, SK_KIND == 6>);
     else
       return nullptr;
