@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
   // in float32 from one float copy of every node.  The y increment row that
   // lane l needs at step t (row t - l) is the one lane l-1 used at step t-1:
   // rows travel down the wave by DPP, and only row t itself is loaded, by a
-  // broadcast load (the same address in every lane) issued one step ahead.
+  // broadcast read (the same LDS address in every lane) one step ahead.
   double u[4] = {1.0, 1.0, 1.0, 1.0};  // nodes K[p0 + r + 1][q] left of column q
   float uf[4] = {1.0f, 1.0f, 1.0f, 1.0f};
   double pub = 1.0;                    // this lane's bottom node after its last column
@@ -99,13 +99,32 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
   float hf[6] = {0, 0, 0, 0, 0, 0};  // the last full block this lane ended
   int hq = -1;                       // its block column, -1: none pending
   const float* __restrict__ ybase = a.incy + pair * (int64_t)n * DP;
-  auto fetch = [&](int q, float (&row)[DP]) {
-    if (q < n) {
-      fwd::load_row<DP>(ybase + (int64_t)q * DP, row);
-    } else {
+  // The rows reach the wave through LDS in blocks of 16: the wave loads
+  // block b (DP / 4 floats per lane, zero past the path) at step 16 (b - 1),
+  // writes it into half b mod 2 of its staging area at step 16 (b - 1) + 12,
+  // and reads row 16 b first at step 16 b - 1; that half's previous block was
+  // last read at step 16 (b - 1) - 2.  The loads so run 12 steps ahead of
+  // their use instead of one.
+  constexpr int PER = DP / 4;
+  __shared__ float ystage[4][2][16 * DP];
+  float (&stage)[2][16 * DP] = ystage[threadIdx.x >> 6];
+  float pend[PER];
+  auto issue = [&](int b) {  // block b's floats of this lane, into pend
 #pragma unroll
-      for (int k = 0; k < DP; ++k) row[k] = 0.0f;
+    for (int i = 0; i < PER; ++i) {
+      const int e = lane * PER + i;
+      const int q = 16 * b + e / DP;
+      pend[i] = q < n ? ybase[(int64_t)16 * b * DP + e] : 0.0f;
     }
+  };
+  auto commit = [&](int b) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) stage[b & 1][lane * PER + i] = pend[i];
+    __builtin_amdgcn_wave_barrier();
+  };
+  auto fetch = [&](int q, float (&row)[DP]) {  // row q of the stream, from LDS
+#pragma unroll
+    for (int k = 0; k < DP; ++k) row[k] = stage[(q >> 4) & 1][(q & 15) * DP + k];
   };
   float dy[DP];
 #pragma unroll
@@ -173,10 +192,16 @@ __global__ __launch_bounds__(256) void features_kernel(const FeatArgs a) {
     if (hq >= 0) put(lane, hq, hf);
     hq = -1;
   };
+  issue(0);
+  commit(0);
+  issue(1);
+  commit(1);
   float dyA[DP], dyB[DP];
   fetch(0, dyA);
   const int nsteps = n + 63;
   for (int t = 0; t < nsteps; t += 4) {
+    if ((t & 15) == 0 && t > 0) issue((t >> 4) + 1);
+    if ((t & 15) == 12 && t > 12) commit((t >> 4) + 1);
     step(t, dyA, dyB);
     step(t + 1, dyB, dyA);
     step(t + 2, dyA, dyB);
