@@ -127,6 +127,54 @@ def test_local_error_bound_single_cell():
         assert err <= oracle.local_error_bound_boundary_one(c) + 1e-15, (c, err)
 
 
+@pytest.mark.parametrize("c", [0.5, 1.0, -1.0])
+def test_local_error_bound_equals_bessel_values(c):
+    # The bound is |c| sup_{z between 0 and c} |I1(2 sqrt z) / sqrt z - 1|.  The
+    # series has positive coefficients and is increasing on [-1, inf), so the
+    # supremum sits at z = c: I1(2 sqrt c) / sqrt c - 1 for c > 0 and
+    # J1(2 sqrt |c|) / sqrt |c| - 1 for c < 0 (SciPy's Bessel routines).  A
+    # looser or tighter bound than the theorem's fails here.
+    r = math.sqrt(abs(c))
+    f = (sp.iv(1, 2 * r) if c > 0 else sp.jv(1, 2 * r)) / r - 1.0
+    want = abs(c) * abs(f)
+    assert abs(oracle.local_error_bound_boundary_one(c) - want) <= 1e-14 * want, c
+    # hand value at c = 1: I1(2) - 1
+    if c == 1.0:
+        assert abs(oracle.local_error_bound_boundary_one(c) - 0.590636854637329) < 1e-14
+
+
+def test_truncation_tail_bound_is_exact_for_parallel_segments():
+    # For x = [0, a] and y = [0, t a] (t > 0), <S^k(x), S^k(y)> = <a, t a>^k / (k!)^2
+    # and |x|_1 |y|_1 = <a, t a>: the bound of the factorial decay and
+    # Cauchy-Schwarz is attained.  The tail is summed by brute force from the
+    # truncated signatures (levels N+1 .. N+11; the levels above add < 1e-19).
+    a = np.array([0.6, -1.1])
+    x = np.array([np.zeros(2), a])
+    y = np.array([np.zeros(2), 1.3 * a])
+    N, top = 3, 14
+    sx = oracle.truncated_signature(x, top)
+    sy = oracle.truncated_signature(y, top)
+    exact = sum(float(np.sum(sx[k] * sy[k])) for k in range(N + 1, top + 1))
+    bound = oracle.truncation_tail_bound(x, y, N)
+    assert abs(bound - exact) <= 1e-13 * exact, (bound, exact)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_truncation_tail_bound_holds_on_random_paths(seed):
+    # the exact levels above N (brute force) stay below the bound, and the bound
+    # is not vacuous: within a factor 10^4 of the level-(N+1) term here
+    rng = np.random.default_rng(seed)
+    x = np.cumsum(rng.normal(0, 0.5, size=(4, 2)), axis=0)
+    y = np.cumsum(rng.normal(0, 0.5, size=(3, 2)), axis=0)
+    N, top = 2, 10
+    sx = oracle.truncated_signature(x, top)
+    sy = oracle.truncated_signature(y, top)
+    levels = [float(np.sum(sx[k] * sy[k])) for k in range(N + 1, top + 1)]
+    bound = oracle.truncation_tail_bound(x, y, N)
+    assert sum(abs(v) for v in levels) <= bound
+    assert bound <= 1e4 * max(abs(levels[0]), 1e-300)
+
+
 # ---------------------------------------------------------------------------
 # Brute-force signatures (definition (signature), Chen's identity)
 # ---------------------------------------------------------------------------
