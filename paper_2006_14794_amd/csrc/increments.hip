@@ -21,13 +21,16 @@ __global__ __launch_bounds__(1024) void plan_kernel(const int64_t* __restrict__ 
   if (threadIdx.x == 0) carry_s = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int64_t cap = n_paths * (int64_t)len;
+  // the points buffer holds off[n_paths] rows; offsets that do not start at 0
+  // break the contract for every path
+  const int64_t end = off[n_paths];
+  const bool first_ok = off[0] == 0;
   for (int64_t base = 0; base < n_paths; base += 1024) {
     const int64_t k = base + threadIdx.x;
     int32_t n = 0;
     if (k < n_paths) {
       const int64_t s = off[k], e = off[k + 1], L = e - s;
-      const bool ok = s >= 0 && L >= 1 && L <= len && e <= cap;
+      const bool ok = first_ok && s >= 0 && L >= 1 && L <= len && e <= end;
       n = ok ? (int32_t)(L - 1) : -1;
       n_out[k] = n;
     }

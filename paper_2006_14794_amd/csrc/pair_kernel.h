@@ -41,16 +41,19 @@ __global__ __launch_bounds__(256) void pair_kernel(const PairArgs a) {
     // next pair of this class (one vector atomic per wave)
     int32_t k = 0;
     if (lane == 0) k = atomicAdd(a.counter, 1);
-    k = __shfl(k, 0, 64);
+    k = __builtin_amdgcn_readlane(k, 0);  // scalar: the task loop's control flow is uniform
     if (k >= count) break;
     const int32_t pid = order[k];
     const int64_t ix = a.gram_ny ? pid / a.gram_ny : pid;
     const int64_t iy = a.gram_ny ? pid - ix * a.gram_ny : pid;
     const int32_t mx = n_inc(a.x_n, a.x_len, ix), my = n_inc(a.y_n, a.y_len, iy);
     if (mx < 0 || my < 0 || mx == 0 || my == 0) {
-      // every lane stores the same value: a lane-0-only store before the
-      // continue has let waves re-enter this loop with a partial exec mask
-      // (and sweep an earlier task again) with this compiler
+      // every lane stores the same value: no lane-dependent branch may precede
+      // a back-edge of this loop.  With a lane-0-only store here the compiler
+      // sent lanes 1..63 straight from that store back to the queue-index
+      // broadcast with the atomic skipped (they cannot be lane 0), so they ran
+      // a second loop header without lane 0 and read lane 0's stale index:
+      // part of the wave swept the previous task again.
       a.out[pid] = (mx < 0 || my < 0) ? __builtin_nanf("") : 1.0f;
       continue;
     }
@@ -176,7 +179,9 @@ __global__ __launch_bounds__(256) void pair_kernel(const PairArgs a) {
       }
       if (!last) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
-    if (lane == 63) a.out[pid] = (float)result;
+    // lane 63 holds the value; every lane stores it (no lane-dependent branch
+    // before the back-edge, see above)
+    a.out[pid] = (float)fwd::lane_value(result, 63);
   }
 }
 
@@ -364,7 +369,7 @@ __device__ __forceinline__ void band_sweep(const PairArgs& a,
     step(t + 2, dyC, dyB, bC, bB);
   }
   // lane 63 holds the value; every lane stores it (see pair_kernel)
-  result = __shfl(result, 63, 64);
+  result = fwd::lane_value(result, 63);
   if (last) a.out[pid] = (float)result;
 }
 
@@ -390,7 +395,7 @@ __global__ __launch_bounds__(256) void pair_band_kernel(const PairArgs a) {
   for (;;) {
     int32_t tau = 0;
     if (lane == 0) tau = atomicAdd(a.task_counter, 1);
-    tau = __shfl(tau, 0, 64);
+    tau = __builtin_amdgcn_readlane(tau, 0);  // scalar (see pair_kernel)
     if (tau >= total_tasks) break;
     // the pair of this task: the last k with task_base[k] <= tau
     int32_t lo = 0, hi = count - 1;

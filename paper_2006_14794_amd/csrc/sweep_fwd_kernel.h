@@ -50,6 +50,14 @@ __device__ __forceinline__ double from_prev_lane(double v, double keep) {
                                           (unsigned long long)(unsigned)lo));
 }
 
+// The value of lane `l`, in scalar registers (uniform for the compiler).
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // 1 / den: the hardware reciprocal refined by two Newton-Raphson steps (each
 // at least squares the relative error), within a few ulp at about half the
 // cost of an IEEE division; 0 gives NaN.

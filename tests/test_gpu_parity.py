@@ -132,6 +132,26 @@ def test_ragged_contract_violation_gives_nan_for_that_pair_only():
     assert mixed_err(got[[0, 2]], ref[[0, 2]]).max() <= TOL
 
 
+def test_ragged_offsets_beyond_the_points_buffer_give_nan():
+    # The points buffer holds offsets[n] rows.  Path 1 below ends at row 22 of a
+    # 20-row buffer (its length, 12, is within the declared bound and its end
+    # within n * len): it must get NaN, not a read past the buffer; path 2 runs
+    # backwards (NaN); path 0 is well formed.  Offsets that do not start at 0
+    # break the contract for every path.
+    pts = workloads.random_paths(31, 1, 20, 3)[0]
+    X = RaggedPaths(cuda(pts), torch.tensor([0, 10, 22, 20], dtype=torch.int64,
+                                            device="cuda"), 12)
+    ys = [workloads.random_paths(32 + i, 1, L, 3)[0] for i, L in enumerate((9, 8, 7))]
+    Y = RaggedPaths.from_list(ys, "cuda")
+    got = sk.sigkernel_pair(X, Y, 1).cpu().numpy()
+    assert np.isnan(got[1]) and np.isnan(got[2])
+    ref = oracle.solve(pts[:10].astype(np.float64), ys[0].astype(np.float64), 1)
+    assert mixed_err(got[0], ref) <= TOL
+    X0 = RaggedPaths(cuda(workloads.random_paths(33, 1, 31, 3)[0]),
+                     torch.tensor([1, 11, 21, 31], dtype=torch.int64, device="cuda"), 12)
+    assert np.all(np.isnan(sk.sigkernel_pair(X0, Y, 1).cpu().numpy()))
+
+
 def test_symmetric_gram_and_no_diag():
     X, _ = workloads.gram_batch(seed=404, n_x=6, n_y=1, n_points=50, dim=4)
     full = sk.sigkernel_gram(cuda(X), cuda(X), 1).cpu().numpy()
