@@ -76,6 +76,27 @@ def sweep_ops_per_cell(d: int, lam: int) -> float:
     return 2.0 + 0.5 * d / float(4 ** lam)
 
 
+def grad_ops_per_cell(d: int, lam: int) -> float:
+    """VALU work per fine cell of the Gram gradient, in FP64-operation
+    equivalents: the forward cell and its share of the coarse inner product
+    (as in sweep_ops_per_cell), the adjoint cell (two double FMAs), its
+    coefficient-gradient product (one FMA) and the two increment contractions
+    (2 d double FMAs per coarse cell, shared by 4^lam fine cells).  The
+    recomputation of the forward values from checkpoints is not counted."""
+    return sweep_ops_per_cell(d, lam) + 3.0 + 2.0 * d / float(4 ** lam)
+
+
+# checkpoint traffic of the gradient kernel per fine cell (written once, read
+# once): R + 2^lam + 1 doubles per lane every C steps of R 2^lam cells, with R
+# = 4 rows per lane and C the segment length (see grad_args.h)
+def grad_checkpoint_bytes_per_cell(d: int, lam: int) -> float:
+    R = 4
+    S = 1 << lam
+    floats_reg = (32 if d > 8 else 64) // (2 if lam == 0 else 1)
+    C = max(1, floats_reg // (R * S)) + max(1, 64 // (R * S))
+    return 2.0 * 8.0 * (R + S + 1) / (R * S * C)
+
+
 # the files the Gram sweep kernel compiles from (its translation unit and headers)
 SWEEP_SOURCES = ("sweep_k0_l1.hip", "sweep_inst.h", "dispatch.h", "sweep_fwd_kernel.h",
                  "sweep_args.h")
@@ -230,8 +251,21 @@ def bench_mmd(args):
     ms = wall * 1e3 / args.steps
     cells = ((L - 1) << lam) ** 2
     fwd_pairs = n * (n - 1) // 2 + m * (m - 1) // 2 + n * m
+    # the gradient solves the off-diagonal upper triangle of Kxx and all of Kxy
     bwd_pairs = n * (n - 1) // 2 + n * m
     work = (fwd_pairs + bwd_pairs) * cells
+    # the dominant kernel on its own: the gradient launch of the cross term
+    # (64 x 64 pairs), with its increments and point-gradient launches, timed
+    # with events over the same number of back-to-back calls
+    wxy = torch.full((n, m), -2.0 / (n * m), dtype=torch.float32, device=dev)
+    ws_b = torch.empty(sk.workspace_bytes(2, Xt, Yt, lam, 0), dtype=torch.uint8, device=dev)
+
+    def cross():
+        sk.sigkernel_gram_backward(Xt, Yt, wxy, lam, need_y=False, workspace=ws_b)
+
+    per_b, _ = time_steps(cross, args.steps, args.warmup)
+    t_b = float(np.mean(per_b)) / 1e3
+    ops = grad_ops_per_cell(d, lam) * n * m * cells
     rec = {
         "metric": "Goursat grid-cell updates/s, MMD^2 forward + adjoint",
         "value": work / (ms / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
@@ -242,15 +276,13 @@ def bench_mmd(args):
                    "forward_pairs": fwd_pairs, "adjoint_pairs": bwd_pairs,
                    "fine_cells_per_pair": cells},
         "avg_event_ms": float(np.mean(per)), "launch": launch,
-        # the adjoint's cell sums: 4 bytes written by the storing forward and
-        # read back by the adjoint per adjoint fine cell (inputs and outputs
-        # are a few MB)
-        "roofline": {"bound": "hbm", "achieved": 8.0 * bwd_pairs * cells / (np.mean(per) / 1e3) / 1e9,
-                     "peak": 8000.0, "unit": "GB/s",
-                     "frac": 8.0 * bwd_pairs * cells / (np.mean(per) / 1e3) / 1e9 / 8000.0,
+        "roofline": {"bound": "alu", "achieved": ops / t_b / 1e12, "peak": VALU_PEAK_TOPS,
+                     "unit": "Tops/s", "frac": ops / t_b / 1e12 / VALU_PEAK_TOPS,
                      "traffic": None,
-                     "kernel": "storing forward + adjoint (events around the timed steps)",
-                     "bytes_per_adjoint_cell": 8},
+                     "kernel": "grad_kernel: gradient of the cross term (64 x 64 pairs), events "
+                               "around the backward call (increments, gradient, point sums)",
+                     "avg_launch_ms": t_b * 1e3, "ops_per_cell": grad_ops_per_cell(d, lam),
+                     "checkpoint_bytes_per_cell": grad_checkpoint_bytes_per_cell(d, lam)},
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -262,9 +294,9 @@ def bench_mmd(args):
         Kyy = oracle.gram(Ys, Ys, lam, nthreads=threads)
         Kxy = oracle.gram(Xs, Ys, lam, nthreads=threads)
         oracle.mmd2_unbiased(Kxx, Kyy, Kxy)
-        wxx, _, wxy = oracle.mmd2_weights(ns, ns)
+        wxx, _, wxy_s = oracle.mmd2_weights(ns, ns)
         oracle.gram_backward(Xs, Xs, wxx, lam, nthreads=threads)
-        oracle.gram_backward(Xs, Ys, wxy, lam, nthreads=threads)
+        oracle.gram_backward(Xs, Ys, wxy_s, lam, nthreads=threads)
         dt = time.perf_counter() - t0
         # the oracle solves full Gram blocks (both halves of the symmetric ones)
         # and both backward blocks in full: count the cells it actually sweeps

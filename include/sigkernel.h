@@ -148,10 +148,20 @@ sk_status sigkernel_gram(const sk_paths *X, const sk_paths *Y, int32_t dyadic_or
  *    sum dK[a][b] K[a][b] over all (a, b) goes to dX and dY must be NULL.
  *    With SK_NO_DIAG as well, the diagonal entries (the constant 0 of the
  *    forward) carry no gradient.
- *  - Uniform batches only (ragged offsets give SK_ERR_UNSUPPORTED).
- *  - Workspace: sigkernel_workspace_bytes(SK_OP_GRAM_BACKWARD, ...); the
- *    forward cell sums (4 bytes per fine cell and pipeline step) of at most
- *    24 GiB worth of pairs are stored at a time, in equal chunks.
+ *  - Uniform or ragged batches (dX / dY then [offsets[n_paths]][dim], like
+ *    the points).  A pair with a broken path (see sk_paths) contributes NaN
+ *    to the gradient of its paths; point rows of a ragged batch that belong
+ *    to no valid path receive NaN.
+ *  - Any x length within the order limit: x paths taller than one band of
+ *    256 fine rows are swept in bands.
+ *  - Method: the forward pass saves the wavefront state every few steps
+ *    (checkpoints, about 0.9 bytes per fine cell at order 1) and the adjoint
+ *    recomputes each stretch of forward values from its checkpoint, bitwise
+ *    as the forward computed them, instead of storing them.
+ *  - Workspace: sigkernel_workspace_bytes(SK_OP_GRAM_BACKWARD, ...): the
+ *    checkpoints of at most 2048 tasks in flight (a task is a run of pairs
+ *    sharing one x path, or one pair of a ragged batch) and the increment
+ *    gradients of every pair, in double.
  */
 sk_status sigkernel_gram_backward(const sk_paths *X, const sk_paths *Y, int32_t dyadic_order,
                                   uint32_t flags, const float *dK, float *dX, float *dY,
@@ -184,7 +194,7 @@ sk_status sigkernel_increment_gram(const sk_paths *X, const sk_paths *Y, int32_t
  *           - 2 sum_{a, b} k(X_a, Y_b) / (n m),     n, m >= 2,
  * with k the explicit scheme on P_lambda.  mmd2: DEVICE float[1].  With
  * SK_MMD2_GRAD, dX (DEVICE, shaped like X's points) receives d MMD^2 / d X;
- * Y is treated as fixed data.  Uniform batches only.  Workspace:
+ * Y is treated as fixed data.  Uniform or ragged batches.  Workspace:
  * sigkernel_workspace_bytes(SK_OP_MMD2, X, Y, dyadic_order, flags).
  */
 sk_status sigkernel_mmd2(const sk_paths *X, const sk_paths *Y, int32_t dyadic_order,

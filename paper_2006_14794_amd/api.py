@@ -291,13 +291,20 @@ def reduced_measure_support(K: torch.Tensor, support: int, iters: int = 3000, ro
     return beta, lam, step_out
 
 
-def sigkernel_gram_backward(X: torch.Tensor, Y: Optional[torch.Tensor], dK: torch.Tensor,
+def _empty_points(P: PathsLike) -> torch.Tensor:
+    """An uninitialised tensor shaped like the points of a batch ([n, len, d],
+    or [total, d] for a ragged batch)."""
+    return torch.empty_like(P.points if isinstance(P, RaggedPaths) else P)
+
+
+def sigkernel_gram_backward(X: PathsLike, Y: Optional[PathsLike], dK: torch.Tensor,
                             dyadic_order: int = 0, *, symmetric: bool = False,
                             no_diag: bool = False, need_x: bool = True, need_y: bool = True,
                             workspace: Optional[torch.Tensor] = None):
     """(dX, dY) = gradients of sum(dK * K) with respect to the points of X and
-    Y (either None when not wanted).  With ``symmetric=True`` Y must be None
-    or X itself and the whole gradient is returned as dX (dY is None)."""
+    Y (either None when not wanted), shaped like their points (ragged batches:
+    [total, d]).  With ``symmetric=True`` Y must be None or X itself and the
+    whole gradient is returned as dX (dY is None)."""
     lib = _lib.load()
     if Y is None:
         Y = X
@@ -316,8 +323,8 @@ def sigkernel_gram_backward(X: torch.Tensor, Y: Optional[torch.Tensor], dK: torc
     dK = dK.contiguous()
     if dK.shape != (_n_paths(X), _n_paths(Y)):
         raise ValueError("dK must be [X.n_paths, Y.n_paths]")
-    dX = torch.empty_like(X) if need_x else None
-    dY = torch.empty_like(Y) if need_y else None
+    dX = _empty_points(X) if need_x else None
+    dY = _empty_points(Y) if need_y else None
     nbytes = int(lib.sigkernel_workspace_bytes(_lib.SK_OP_GRAM_BACKWARD, ctypes.byref(sx),
                                                ctypes.byref(sy), int(dyadic_order), flags))
     ws = _workspace(nbytes, dev, workspace)
@@ -373,7 +380,7 @@ def gram(X: torch.Tensor, Y: Optional[torch.Tensor] = None, dyadic_order: int = 
     return SigKernelGram.apply(X, Y, dyadic_order)
 
 
-def sigkernel_mmd2(X: torch.Tensor, Y: torch.Tensor, dyadic_order: int = 0, *,
+def sigkernel_mmd2(X: PathsLike, Y: PathsLike, dyadic_order: int = 0, *,
                    grad: bool = False, workspace: Optional[torch.Tensor] = None):
     """(mmd2 [1] device tensor, dX or None): unbiased MMD^2 between the batches
     and, with ``grad=True``, its gradient with respect to the points of X."""
@@ -382,7 +389,7 @@ def sigkernel_mmd2(X: torch.Tensor, Y: torch.Tensor, dyadic_order: int = 0, *,
     flags = _lib.SK_MMD2_GRAD if grad else 0
     sx, sy = _describe(X), _describe(Y)
     out = torch.empty(1, dtype=torch.float32, device=dev)
-    dX = torch.empty_like(X) if grad else None
+    dX = _empty_points(X) if grad else None
     nbytes = int(lib.sigkernel_workspace_bytes(_lib.SK_OP_MMD2, ctypes.byref(sx),
                                                ctypes.byref(sy), int(dyadic_order), flags))
     ws = _workspace(nbytes, dev, workspace)

@@ -277,60 +277,68 @@ size_t gram_ws(const sk_paths* X, const sk_paths* Y, int32_t lam) {
   return f > g ? f : g;
 }
 
-// Backward workspace: the forward layout, then the per-wave store of one
-// chunk of waves, the per-run x-side and per-pair y-side increment gradients.
-// The store of a chunk is capped (HBM holds 288 GB); the waves are split into
-// chunks of equal size, so that every launch still fills the chip.
-constexpr size_t kStoreCapBytes = size_t(24) << 30;
+// Gram gradient workspace: the forward layout (increments, and the plans of
+// ragged batches), the task order of a ragged batch, counters, one scratch
+// slot per persistent wave (checkpoints and band hand-overs), and the x-side
+// and y-side increment gradients in double.  The persistent waves are a
+// constant number (two per SIMD of the target), so that the workspace size
+// does not depend on the device queried.
+constexpr int64_t kGradSlots = 2048;
 
-struct BackwardPlan {
-  int R, waves_per_block;
-  int64_t run, runs_per_row, n_waves;
-  int64_t store_stride;  // floats per wave
-  int64_t chunk;         // waves per chunk
-  size_t store_off, partx_off, party_off, total;
+struct GradPlan {
+  int lam, rep;
+  bool ragged;
+  int64_t run, runs_per_row, n_tasks, slots;
+  int nb_max, nseg_max;
+  int64_t cols_max;
+  int32_t mrows, nrows;
+  int64_t slot_stride;  // doubles
+  size_t order, counts, scratch, partx, party, total;
 };
 
-BackwardPlan backward_plan(const sk_paths* X0, const sk_paths* Y0, int32_t lam0,
-                           uint32_t flags) {
+GradPlan grad_plan(const sk_paths* X0, const sk_paths* Y0, int32_t lam0, uint32_t flags) {
   const Order o = split_order(lam0);
   const sk_paths Xr = refined(X0, o.rep), Yr = refined(Y0, o.rep);
-  const sk_paths* X = &Xr;
-  const sk_paths* Y = &Yr;
-  const int32_t lam = o.k;
-  BackwardPlan P{};
-  const int64_t m = X->len - 1, n = Y->len - 1;
-  const int64_t fine_rows = m << lam;
-  P.R = sk::choose_rows_per_lane(fine_rows < 1 ? 1 : fine_rows, lam, X->dim);
-  if (P.R == 0) {  // no compiled configuration: the caller reports SK_ERR_UNSUPPORTED
-    P.total = forward_ws(X, Y);
-    return P;
+  GradPlan P{};
+  P.lam = o.k;
+  P.rep = o.rep;
+  P.ragged = X0->offsets || Y0->offsets;
+  const int64_t m = Xr.len > 1 ? Xr.len - 1 : 0, n = Yr.len > 1 ? Yr.len - 1 : 0;
+  const int d = X0->dim;
+  P.mrows = (int32_t)m;
+  P.nrows = (int32_t)n;
+  if (P.ragged) {
+    P.run = 1;
+    P.runs_per_row = Y0->n_paths;
+  } else {
+    const sk_tune t = sk::tuning_for(SK_OP_GRAM_BACKWARD, X0, Y0, lam0, flags);
+    P.run = choose_run(X0->n_paths, Y0->n_paths, t.run);
+    P.runs_per_row = (Y0->n_paths + P.run - 1) / P.run;
   }
-  const sk_tune t = sk::tuning_for(SK_OP_GRAM_BACKWARD, X0, Y0, lam0, flags);
-  P.waves_per_block = t.waves_per_block;
-  P.run = choose_run(X->n_paths, Y->n_paths, t.run);
-  P.runs_per_row = (Y->n_paths + P.run - 1) / P.run;
-  P.n_waves = X->n_paths * P.runs_per_row;
-  const int64_t rs = sk::cell_group_floats(P.R << lam);
-  P.store_stride = sk::sweep_steps(P.run * (n > 0 ? n : 1)) * 64 * rs;
-  const int64_t per_wave = P.store_stride * (int64_t)sizeof(float);
-  int64_t fit = (int64_t)(kStoreCapBytes / (size_t)per_wave);
-  if (fit < 1) fit = 1;
-  const int64_t nchunks = (P.n_waves + fit - 1) / fit;
-  P.chunk = nchunks > 0 ? (P.n_waves + nchunks - 1) / nchunks : 1;
-  size_t off = forward_ws(X, Y);
-  P.store_off = off;
-  off += align256((size_t)P.chunk * (size_t)per_wave);
-  P.partx_off = off;
-  off += align256((size_t)P.n_waves * (size_t)(m > 0 ? m : 0) * X->dim * sizeof(float));
-  P.party_off = off;
-  off += align256((size_t)X->n_paths * Y->n_paths * (size_t)(n > 0 ? n : 0) * X->dim *
-                  sizeof(float));
+  P.n_tasks = X0->n_paths * P.runs_per_row;
+  P.slots = P.n_tasks < kGradSlots ? P.n_tasks : kGradSlots;
+  if (P.slots < 1) P.slots = 1;
+  const int64_t M = m << P.lam;
+  const int64_t band_rows = 64 * (int64_t)sk::kGradRows;
+  P.nb_max = (int)(M > 0 ? (M + band_rows - 1) / band_rows : 1);
+  P.cols_max = P.run * (n > 0 ? n : 1);
+  const int C = sk::grad_segment(P.lam, d);
+  P.nseg_max = (int)((P.cols_max + 63 + C - 1) / C);
+  P.slot_stride = sk::grad_slot_layout(P.lam, P.nb_max, P.nseg_max, P.cols_max).stride;
+  size_t off = forward_ws(&Xr, &Yr);
+  P.order = off;
+  if (P.ragged) off += align256((size_t)(P.n_tasks > 0 ? P.n_tasks : 1) * sizeof(int32_t));
+  P.counts = off;
+  off += 256;  // the pair plan's counts and counters, the gradient queue head
+  P.scratch = off;
+  off += align256((size_t)P.slots * (size_t)P.slot_stride * sizeof(double));
+  P.partx = off;
+  off += align256((size_t)X0->n_paths * (size_t)P.runs_per_row * (size_t)m * d * sizeof(double));
+  P.party = off;
+  off += align256((size_t)X0->n_paths * Y0->n_paths * (size_t)n * d * sizeof(double));
   P.total = off;
   return P;
 }
-
-
 
 int rounding_of(uint32_t flags) {
   if (flags & SK_GRAM_BF16) return sk::kRoundBf16;
@@ -639,10 +647,10 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam0, uint32
 }
 
 // MMD^2 workspace: the three Gram blocks, the two upstream weight matrices,
-// a temporary gradient, then the largest workspace of the calls it makes
+// then the largest workspace of the calls it makes
 // (they run one after the other on the stream and share it).
 struct Mmd2Layout {
-  size_t kxx, kyy, kxy, wxx, wxy, tmp, sub, sub_bytes, total;
+  size_t kxx, kyy, kxy, wxx, wxy, sub, sub_bytes, total;
 };
 
 Mmd2Layout mmd2_layout(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t flags) {
@@ -659,14 +667,12 @@ Mmd2Layout mmd2_layout(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32
   off += align256(n * n * sizeof(float));
   L.wxy = off;
   off += align256(n * m * sizeof(float));
-  L.tmp = off;
-  off += align256((size_t)X->n_paths * X->len * X->dim * sizeof(float));
   size_t sub = gram_ws(X, X, lam);
   const size_t c[] = {gram_ws(Y, Y, lam), gram_ws(X, Y, lam)};
   for (size_t v : c) sub = v > sub ? v : sub;
   if (flags & SK_MMD2_GRAD) {
-    const size_t b1 = backward_plan(X, X, lam, SK_SYMMETRIC | SK_NO_DIAG).total;
-    const size_t b2 = backward_plan(X, Y, lam, 0).total;
+    const size_t b1 = grad_plan(X, X, lam, SK_SYMMETRIC | SK_NO_DIAG).total;
+    const size_t b2 = grad_plan(X, Y, lam, 0).total;
     sub = b1 > sub ? b1 : sub;
     sub = b2 > sub ? b2 : sub;
   }
@@ -909,10 +915,10 @@ size_t sigkernel_workspace_bytes(int32_t op, const sk_paths* X, const sk_paths* 
     case SK_OP_GRAM:
       return gram_ws(X, Y, dyadic_order);
     case SK_OP_GRAM_BACKWARD:
-      if (X->offsets || Y->offsets || X->dim != Y->dim) return 0;
-      return backward_plan(X, Y, dyadic_order, flags).total;
+      if (X->dim != Y->dim) return 0;
+      return grad_plan(X, Y, dyadic_order, flags).total;
     case SK_OP_MMD2:
-      if (X->offsets || Y->offsets || X->dim != Y->dim) return 0;
+      if (X->dim != Y->dim) return 0;
       return mmd2_layout(X, Y, dyadic_order, flags).total;
     case SK_OP_CORRECTOR_FEATURES:
       if (check_corrector_batches(X, Y) == SK_ERR_SHAPE) return 0;
@@ -1090,7 +1096,7 @@ sk_status sigkernel_increment_gram(const sk_paths* X, const sk_paths* Y, int32_t
 
 static sk_status gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
                                uint32_t flags, const float* dK, float* dX, float* dY, float* K,
-                               void* ws, size_t ws_bytes, void* stream);
+                               bool accumulate, void* ws, size_t ws_bytes, void* stream);
 
 sk_status sigkernel_mmd2(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
                          uint32_t flags, float* mmd2, float* dX, void* ws, size_t ws_bytes,
@@ -1101,7 +1107,6 @@ sk_status sigkernel_mmd2(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
   if (!order_ok(dyadic_order, X, Y, kMaxDyadicOrder)) return SK_ERR_ORDER;
   if (sk_status f = check_flags(flags, SK_MMD2_GRAD)) return f;
   if ((flags & SK_MMD2_GRAD) && !dX) return SK_ERR_NULL;
-  if (X->offsets || Y->offsets) return SK_ERR_UNSUPPORTED;
   if (!X->points || !Y->points) return SK_ERR_NULL;
   if (!ws) return SK_ERR_WORKSPACE;
   const Mmd2Layout L = mmd2_layout(X, Y, dyadic_order, flags);
@@ -1114,9 +1119,10 @@ sk_status sigkernel_mmd2(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
   void* sub = base + L.sub;
   const uint32_t unb = SK_SYMMETRIC | SK_NO_DIAG;
   const bool grad = (flags & SK_MMD2_GRAD) != 0;
-  // with the gradient, Kxx and Kxy come from the backward's storing forwards
-  // (which sweep paths of at least two points)
-  const bool fused = grad && X->len >= 2 && Y->len >= 2;
+  // with the gradient, Kxx and Kxy come from the gradient launches' forward
+  // passes (which a uniform batch of one-point paths skips)
+  const bool ragged = X->offsets || Y->offsets;
+  const bool fused = grad && (ragged || (X->len >= 2 && Y->len >= 2));
   sk_status r;
   if (!fused && (r = sigkernel_gram(X, X, dyadic_order, unb, kxx, sub, L.sub_bytes, stream)))
     return r;
@@ -1127,7 +1133,6 @@ sk_status sigkernel_mmd2(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
     const int64_t n = X->n_paths, m = Y->n_paths;
     float* wxx = reinterpret_cast<float*>(base + L.wxx);
     float* wxy = reinterpret_cast<float*>(base + L.wxy);
-    float* tmp = reinterpret_cast<float*>(base + L.tmp);
     // d MMD^2 / d Kxx[a][b] = 1 / (n (n - 1)) off the diagonal (the symmetric
     // backward ignores the diagonal); d MMD^2 / d Kxy[a][b] = -2 / (n m)
     if (sk::launch_fill(wxx, n * n, (float)(1.0 / ((double)n * (double)(n - 1))), st) !=
@@ -1135,14 +1140,13 @@ sk_status sigkernel_mmd2(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
       return SK_ERR_HIP;
     if (sk::launch_fill(wxy, n * m, (float)(-2.0 / ((double)n * (double)m)), st) != hipSuccess)
       return SK_ERR_HIP;
-    if ((r = gram_backward(X, X, dyadic_order, unb, wxx, dX, nullptr, fused ? kxx : nullptr, sub,
-                           L.sub_bytes, stream)))
+    if ((r = gram_backward(X, X, dyadic_order, unb, wxx, dX, nullptr, fused ? kxx : nullptr,
+                           false, sub, L.sub_bytes, stream)))
       return r;
-    if ((r = gram_backward(X, Y, dyadic_order, 0, wxy, tmp, nullptr, fused ? kxy : nullptr, sub,
-                           L.sub_bytes, stream)))
+    // the cross term's gradient is added to dX by its point-gradient launch
+    if ((r = gram_backward(X, Y, dyadic_order, 0, wxy, dX, nullptr, fused ? kxy : nullptr, true,
+                           sub, L.sub_bytes, stream)))
       return r;
-    if (sk::launch_add(dX, tmp, X->n_paths * X->len * X->dim, st) != hipSuccess)
-      return SK_ERR_HIP;
   }
   if (sk::launch_mmd2_reduce(kxx, X->n_paths, kyy, Y->n_paths, kxy, mmd2, st) != hipSuccess)
     return SK_ERR_HIP;
@@ -1150,11 +1154,12 @@ sk_status sigkernel_mmd2(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
 }
 
 // The Gram backward; K (optional) receives the forward values of the same
-// pairs, as sigkernel_gram with the same flags would write them (the storing
-// forward computes them anyway).
+// pairs, as sigkernel_gram with the same flags would write them (the
+// gradient launch's forward pass computes them anyway); accumulate: dX +=
+// instead of dX = (the MMD's cross term).
 static sk_status gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
                                uint32_t flags, const float* dK, float* dX, float* dY, float* K,
-                               void* ws, size_t ws_bytes, void* stream) {
+                               bool accumulate, void* ws, size_t ws_bytes, void* stream) {
   if (!X || !Y) return SK_ERR_NULL;
   if (!valid_batch(X) || !valid_batch(Y)) return SK_ERR_SHAPE;
   if (X->dim != Y->dim) return SK_ERR_SHAPE;
@@ -1165,25 +1170,28 @@ static sk_status gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dya
               X->len != Y->len))
     return SK_ERR_SHAPE;
   if (sym && dY) return SK_ERR_SHAPE;  // one batch: its gradient goes to dX
-  if (X->offsets || Y->offsets) return SK_ERR_UNSUPPORTED;
   if (X->n_paths == 0 || Y->n_paths == 0) return SK_OK;
   if (!dK || (!dX && !dY)) return SK_ERR_NULL;
-  if ((X->n_paths > 0 && !X->points) || (Y->n_paths > 0 && !Y->points)) return SK_ERR_NULL;
+  if (!X->points || !Y->points) return SK_ERR_NULL;
+  if (X->n_paths * Y->n_paths > INT32_MAX) return SK_ERR_UNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Order o = split_order(dyadic_order);
   const int lam = o.k;
   const sk_paths Xr = refined(X, o.rep), Yr = refined(Y, o.rep);
   const int d = X->dim;
-  // one-point paths: the kernel is the constant 1, every gradient is 0
-  if (X->len < 2 || Y->len < 2) {
+  const bool ragged = X->offsets || Y->offsets;
+  // uniform batches of one-point paths: the kernel is the constant 1, every
+  // gradient is 0
+  if (!ragged && (X->len < 2 || Y->len < 2)) {
+    if (accumulate) return SK_OK;
     if (dX && sk::launch_fill(dX, X->n_paths * X->len * d, 0.0f, st) != hipSuccess)
       return SK_ERR_HIP;
     if (dY && sk::launch_fill(dY, Y->n_paths * Y->len * d, 0.0f, st) != hipSuccess)
       return SK_ERR_HIP;
     return SK_OK;
   }
-  const BackwardPlan P = backward_plan(X, Y, dyadic_order, flags);
-  if (P.R == 0 || !sk::adjoint_supported(P.R, lam, d)) return SK_ERR_UNSUPPORTED;
+  if (!sk::grad_supported(lam, d)) return SK_ERR_UNSUPPORTED;
+  const GradPlan P = grad_plan(X, Y, dyadic_order, flags);
   if (!ws) return SK_ERR_WORKSPACE;
   if (ws_bytes < P.total) return SK_ERR_WORKSPACE;
 
@@ -1192,82 +1200,114 @@ static sk_status gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dya
   char* base = static_cast<char*>(ws);
   float* incx = reinterpret_cast<float*>(base + L.incx) + sk::kStreamPad * dp;
   float* incy = reinterpret_cast<float*>(base + L.incy) + sk::kStreamPad * dp;
-  float* store = reinterpret_cast<float*>(base + P.store_off);
-  float* part_x = reinterpret_cast<float*>(base + P.partx_off);
-  float* part_y = reinterpret_cast<float*>(base + P.party_off);
+  sk::PathPlan px{reinterpret_cast<int32_t*>(base + L.planx_n),
+                  reinterpret_cast<int64_t*>(base + L.planx_start)};
+  sk::PathPlan py{reinterpret_cast<int32_t*>(base + L.plany_n),
+                  reinterpret_cast<int64_t*>(base + L.plany_start)};
   const sk::Batch bx = to_batch(X), by = to_batch(Y);
   const float scale = ldexpf(1.0f, -(2 * lam + 1));
-  if (sk::launch_increments(bx, nullptr, scale, dp, incx, st, sk::kRoundNone, o.rep) !=
-      hipSuccess)
+  if (X->offsets && sk::launch_plan(bx, px, st) != hipSuccess) return SK_ERR_HIP;
+  if (Y->offsets && sk::launch_plan(by, py, st) != hipSuccess) return SK_ERR_HIP;
+  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, scale, dp, incx, st,
+                            sk::kRoundNone, o.rep) != hipSuccess)
     return SK_ERR_HIP;
-  if (sk::launch_increments(by, nullptr, 1.0f, dp, incy, st, sk::kRoundNone, o.rep) !=
-      hipSuccess)
+  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, st, sk::kRoundNone,
+                            o.rep) != hipSuccess)
+    return SK_ERR_HIP;
+  if (X->offsets && sk::launch_scale_plan(px, X->n_paths, o.rep, st) != hipSuccess)
+    return SK_ERR_HIP;
+  if (Y->offsets && sk::launch_scale_plan(py, Y->n_paths, o.rep, st) != hipSuccess)
     return SK_ERR_HIP;
 
-  sk::SweepArgs fa{};
-  fa.incx = incx;
-  fa.incy = incy;
-  fa.x_len = Xr.len;
-  fa.y_len = Yr.len;
-  fa.nx = X->n_paths;
-  fa.ny = Y->n_paths;
-  fa.mode = sym ? 2 : 1;
-  fa.no_diag = (K && (flags & SK_NO_DIAG)) ? 1 : 0;
-  fa.run = (int32_t)P.run;
-  fa.runs_per_row = P.runs_per_row;
-  fa.out = K;
-  fa.out_ld = Y->n_paths;
-  fa.store = store;
-  fa.store_stride = P.store_stride;
-
-  sk::BwdArgs ba{};
-  ba.incx = incx;
-  ba.incy = incy;
-  ba.x_len = Xr.len;
-  ba.y_len = Yr.len;
-  ba.nx = X->n_paths;
-  ba.ny = Y->n_paths;
-  ba.mode = sym ? 2 : 1;
-  ba.no_diag = (flags & SK_NO_DIAG) ? 1 : 0;
-  ba.run = (int32_t)P.run;
-  ba.runs_per_row = P.runs_per_row;
-  ba.dK = dK;
-  ba.store = store;
-  ba.store_stride = P.store_stride;
-  ba.part_x = part_x;
-  ba.part_y = part_y;
-  for (int64_t w0 = 0; w0 < P.n_waves; w0 += P.chunk) {
-    const int64_t nw = (P.n_waves - w0) < P.chunk ? (P.n_waves - w0) : P.chunk;
-    fa.wave0 = w0;
-    fa.n_waves = nw;
-    if (sk::launch_sweep_store(fa, lam, P.R, d, st, P.waves_per_block) != hipSuccess)
-      return SK_ERR_HIP;
-    ba.wave0 = w0;
-    ba.n_waves = nw;
-    if (sk::launch_adjoint(ba, lam, P.R, d, st, P.waves_per_block) != hipSuccess)
-      return SK_ERR_HIP;
+  int32_t* counts = reinterpret_cast<int32_t*>(base + P.counts);
+  int32_t* order = nullptr;
+  if (ragged) {
+    // one task per pair, costliest first (the ordering only steers scheduling)
+    order = reinterpret_cast<int32_t*>(base + P.order);
+    sk::PairPlanArgs pp{};
+    pp.x_n = X->offsets ? px.n : nullptr;
+    pp.x_len = Xr.len;
+    pp.y_n = Y->offsets ? py.n : nullptr;
+    pp.y_len = Yr.len;
+    pp.npairs = (int32_t)P.n_tasks;
+    pp.gram_ny = Y->n_paths;
+    pp.lam = lam;
+    pp.rows_lo = 0;  // one class
+    pp.rows_hi = sk::kGradRows;
+    pp.order = order;
+    pp.counts = counts;
+    pp.counters = counts + 2;
+    if (sk::launch_pair_plan(pp, st) != hipSuccess) return SK_ERR_HIP;
   }
+
+  sk::GradArgs ga{};
+  ga.incx = incx;
+  ga.incy = incy;
+  ga.x_n = X->offsets ? px.n : nullptr;
+  ga.x_start = X->offsets ? px.start : nullptr;
+  ga.y_n = Y->offsets ? py.n : nullptr;
+  ga.y_start = Y->offsets ? py.start : nullptr;
+  ga.x_len = Xr.len;
+  ga.y_len = Yr.len;
+  ga.nx = X->n_paths;
+  ga.ny = Y->n_paths;
+  ga.mode = sym ? 2 : 1;
+  ga.no_diag = (flags & SK_NO_DIAG) ? 1 : 0;
+  ga.run = (int32_t)P.run;
+  ga.runs_per_row = P.runs_per_row;
+  ga.n_tasks = (int32_t)P.n_tasks;
+  ga.order = order;
+  ga.counter = counts + 4;
+  ga.dK = dK;
+  ga.K = K;
+  ga.scratch = reinterpret_cast<double*>(base + P.scratch);
+  ga.slot_stride = P.slot_stride;
+  ga.nb_max = P.nb_max;
+  ga.nseg_max = P.nseg_max;
+  ga.cols_max = P.cols_max;
+  ga.part_x = reinterpret_cast<double*>(base + P.partx);
+  ga.part_y = reinterpret_cast<double*>(base + P.party);
+  ga.mrows = P.mrows;
+  ga.nrows = P.nrows;
+  if (sk::launch_grad(ga, lam, d, P.slots, st) != hipSuccess) return SK_ERR_HIP;
+
   // the parts of a refined increment are the increment over rep: their
   // gradients sum, times 1 / rep, to the increment's
-  const float inv_rep = 1.0f / (float)o.rep;
-  if (dX) {
-    if (sk::launch_point_grad(part_x, P.runs_per_row, scale * inv_rep, sym ? part_y : nullptr,
-                              X->n_paths, Y->n_paths, sym, inv_rep, o.rep, X->n_paths, X->len, d,
-                              dX, st) != hipSuccess)
-      return SK_ERR_HIP;
-  }
-  if (dY) {
-    if (sk::launch_point_grad(nullptr, 0, 1.0f, part_y, X->n_paths, Y->n_paths, false, inv_rep,
-                              o.rep, Y->n_paths, Y->len, d, dY, st) != hipSuccess)
-      return SK_ERR_HIP;
-  }
+  const double inv_rep = 1.0 / (double)o.rep;
+  auto points = [&](const sk_paths* B, const sk::PathPlan& plan, bool x_side, float* out,
+                    bool acc) -> hipError_t {
+    sk::GradPointArgs g{};
+    g.part_x = x_side ? ga.part_x : nullptr;
+    g.runs_per_row = P.runs_per_row;
+    g.mrows = P.mrows;
+    g.part_y = (!x_side || sym) ? ga.part_y : nullptr;
+    g.py_rows = X->n_paths;
+    g.py_ld = Y->n_paths;
+    g.nrows = P.nrows;
+    g.col_upper = sym ? 1 : 0;
+    g.xscale = (double)scale * inv_rep;
+    g.yscale = inv_rep;
+    g.rep = o.rep;
+    g.offsets = B->offsets;
+    g.plan_n = B->offsets ? plan.n : nullptr;
+    g.n_paths = B->n_paths;
+    g.len = B->len;
+    g.d = d;
+    g.rows_bound = B->n_paths * (int64_t)B->len;
+    g.accumulate = acc ? 1 : 0;
+    g.out = out;
+    return sk::launch_grad_points(g, st);
+  };
+  if (dX && points(X, px, true, dX, accumulate) != hipSuccess) return SK_ERR_HIP;
+  if (dY && points(Y, py, false, dY, false) != hipSuccess) return SK_ERR_HIP;
   return SK_OK;
 }
 
 sk_status sigkernel_gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
                                   uint32_t flags, const float* dK, float* dX, float* dY, void* ws,
                                   size_t ws_bytes, void* stream) {
-  return gram_backward(X, Y, dyadic_order, flags, dK, dX, dY, nullptr, ws, ws_bytes, stream);
+  return gram_backward(X, Y, dyadic_order, flags, dK, dX, dY, nullptr, false, ws, ws_bytes,
+                       stream);
 }
 
 // ---- learned corrector ----------------------------------------------------

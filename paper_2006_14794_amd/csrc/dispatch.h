@@ -22,12 +22,6 @@ constexpr int max_fitting_rows(int LAM, int D) {
   return r;
 }
 
-// The adjoint keeps a second x-increment row, the gradient accumulators and
-// the stored cell sums in registers as well: a tighter budget (no spills).
-constexpr bool adjoint_fits(int R, int LAM, int D) {
-  return ((R >> LAM) > 0 ? (R >> LAM) : 1) * D <= 72 && R <= 16;
-}
-
 // The lifted sweep keeps the x nodes (coarse rows + 1) instead of the
 // increments, plus the previous column's row differences.
 constexpr bool lifted_fits(int R, int LAM, int D) {

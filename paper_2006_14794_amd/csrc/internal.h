@@ -60,6 +60,7 @@ hipError_t launch_nodes(const Batch& b, const PathPlan* plan, int dpad, float* n
 
 }  // namespace sk
 
+#include "grad_args.h"
 #include "sweep_args.h"
 
 namespace sk {
@@ -74,8 +75,6 @@ int choose_rows_per_lane(int64_t fine_rows, int lam, int dim);
 // waves_per_block: 1, 2 or 4 one-wave sweeps per workgroup (0: 4).
 hipError_t launch_sweep(const SweepArgs& a, int lam, int rows_per_lane, int dim,
                         hipStream_t stream, int waves_per_block = 0);
-hipError_t launch_sweep_store(const SweepArgs& a, int lam, int rows_per_lane, int dim,
-                              hipStream_t stream, int waves_per_block = 0);
 // The sweep of the Gaussian-lifted kernel (lifted_kernel.h): incx / incy hold
 // node rows, lift_inv and lift_scale are set.
 hipError_t launch_lifted(const SweepArgs& a, int lam, int rows_per_lane, int dim,
@@ -84,35 +83,34 @@ hipError_t launch_lifted(const SweepArgs& a, int lam, int rows_per_lane, int dim
 // rows (0 if none).
 int choose_rows_for(int kind, int64_t fine_rows, int lam, int dim);
 
-// Adjoint sweep of a Gram batch (uniform batches).
-struct BwdArgs {
-  const float* incx;        // dense x increments, pre-scaled by 2^-(2 lam + 1)
-  const float* incy;        // dense y increments
-  int32_t x_len, y_len;     // points per path (both >= 2)
-  int64_t nx, ny;
-  int32_t mode;             // 1: Gram; 2: upper triangle of a symmetric Gram
-  int32_t no_diag;          // mode 2: diagonal pairs carry no gradient
-  int32_t run;
-  int64_t runs_per_row;
-  int64_t wave0, n_waves;   // waves launched
-  const float* dK;          // upstream weights [nx][ny]
-  const float* store;       // forward S values of the launched waves
-  int64_t store_stride;     // floats per wave
-  float* part_x;            // [all waves][x_len - 1][dim]: x-side increment gradients per run
-  float* part_y;            // [nx][ny][y_len - 1][dim]: y-side increment gradients per pair
-};
+// Gradient of weighted Gram entries (grad_kernel.h, grad.hip): persistent
+// waves over the tasks of a GradArgs, `slots` of them, each with its own
+// scratch slot (the queue counter is zeroed by a kernel first).
+hipError_t launch_grad(const GradArgs& a, int lam, int dim, int64_t slots, hipStream_t stream);
+bool grad_supported(int lam, int dim);
 
-hipError_t launch_adjoint(const BwdArgs& a, int lam, int rows_per_lane, int dim,
-                          hipStream_t stream, int waves_per_block = 0);
-bool adjoint_supported(int rows_per_lane, int lam, int dim);
-// Point gradients of a Gram batch from the partial increment gradients:
-// increment p of path k collects rows p rep .. p rep + rep - 1 of its x-side
-// partials (summed over runs, times scale) and y-side partials (summed over
-// the other batch, times yscale); then dx_i = dinc_{i-1} - dinc_i.
-hipError_t launch_point_grad(const float* part_x, int64_t runs_per_row, float scale,
-                             const float* part_y, int64_t part_y_rows, int64_t part_y_ld,
-                             bool col_upper, float yscale, int32_t rep, int64_t n_paths,
-                             int32_t len, int32_t d, float* out, hipStream_t stream);
+// Point gradients of one batch from a gradient launch's increment gradients
+// (grad.hip): see grad_points_kernel.
+struct GradPointArgs {
+  const double* part_x;     // [n_paths][runs_per_row][mrows][d] or nullptr
+  int64_t runs_per_row;
+  int32_t mrows;
+  const double* part_y;     // [py_rows][py_ld][nrows][d] or nullptr; path k is column k
+  int64_t py_rows, py_ld;
+  int32_t nrows;
+  int32_t col_upper;        // symmetric Gram: rows a <= k only
+  double xscale, yscale;
+  int32_t rep;
+  const int64_t* offsets;   // ragged batch (device) or nullptr
+  const int32_t* plan_n;    // ragged: increments per path (-1: broken)
+  int64_t n_paths;
+  int32_t len;              // uniform: points per path
+  int32_t d;
+  int64_t rows_bound;       // point rows covered by the launch (uniform: all; ragged: a bound)
+  int32_t accumulate;       // 1: out += the gradient; 0: out = the gradient
+  float* out;               // [rows][d]
+};
+hipError_t launch_grad_points(const GradPointArgs& a, hipStream_t stream);
 
 hipError_t launch_mmd2_reduce(const float* kxx, int64_t n, const float* kyy, int64_t m,
                               const float* kxy, float* out, hipStream_t stream);
@@ -249,9 +247,8 @@ hipError_t launch_gram_mfma(const GramArgs& a, int precision, hipStream_t stream
 
 // Compiled sweep kernels by kind, dyadic order, rows per lane and channels
 // (nullptr when the configuration is not compiled).
-enum { kKernelForward = 0, kKernelForwardStore = 1, kKernelAdjoint = 2, kKernelPair = 3,
-       kKernelLifted = 4, kKernelForwardImplicit = 5, kKernelPairBand = 6,
-       kKernelPairBandFull = 7 };
+enum { kKernelForward = 0, kKernelPair = 3, kKernelLifted = 4, kKernelForwardImplicit = 5,
+       kKernelPairBand = 6, kKernelPairBandFull = 7 };
 void* sweep_fn(int kind, int lam, int rows_per_lane, int dim);
 
 }  // namespace sk

@@ -31,10 +31,6 @@ struct SweepArgs {
   int64_t out_ld;           // ny for the Gram
   // waves [wave0, wave0 + n_waves) of the run enumeration are launched
   int64_t wave0;
-  // adjoint support: per wave, nsteps x 64 lanes x (R 2^lam) floats (the
-  // cell-sum layout below)
-  float* store;
-  int64_t store_stride;
   // coefficient sweep: per launched wave, coef_stride floats of pre-scaled
   // coarse coefficients in step order ([step][lane][coarse row of the strip])
   const float* coef;
@@ -51,36 +47,6 @@ constexpr int64_t kStreamPad = 128;
 // the y-row prefetch rotates three buffers).
 __host__ __device__ inline int64_t sweep_steps(int64_t total) {
   return ((total + 63 + 2) / 3) * 3;
-}
-
-// Cell sums stored for the adjoint: per wave and step, the R 2^lam floats of
-// each of the 64 lanes, interleaved by groups of four, [group][lane][4], so
-// that one 16-byte access of the wave covers one contiguous kilobyte.  A step
-// holds 64 * cell_group_floats(rs) floats (rs rounded up to a multiple of 4).
-__host__ __device__ constexpr int cell_group_floats(int rs) { return (rs + 3) & ~3; }
-
-// The rs floats of one lane at p = step base + 4 * lane.
-template <int RS>
-__device__ __forceinline__ void put_cells(float* __restrict__ p, const float (&v)[RS]) {
-#pragma unroll
-  for (int g = 0; g < RS / 4; ++g)
-    *reinterpret_cast<float4*>(p + 256 * g) =
-        make_float4(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]);
-#pragma unroll
-  for (int i = (RS / 4) * 4; i < RS; ++i) p[256 * (RS / 4) + (i & 3)] = v[i];
-}
-template <int RS>
-__device__ __forceinline__ void get_cells(const float* __restrict__ p, float (&v)[RS]) {
-#pragma unroll
-  for (int g = 0; g < RS / 4; ++g) {
-    const float4 t = *reinterpret_cast<const float4*>(p + 256 * g);
-    v[4 * g] = t.x;
-    v[4 * g + 1] = t.y;
-    v[4 * g + 2] = t.z;
-    v[4 * g + 3] = t.w;
-  }
-#pragma unroll
-  for (int i = (RS / 4) * 4; i < RS; ++i) v[i] = p[256 * (RS / 4) + (i & 3)];
 }
 
 }  // namespace sk

@@ -6,8 +6,6 @@ namespace sk {
 
 #define SK_DECL(k, l) void* sweep_fn_k##k##_l##l##_(int R, int d);
 SK_DECL(0, 0) SK_DECL(0, 1) SK_DECL(0, 2) SK_DECL(0, 3)
-SK_DECL(1, 0) SK_DECL(1, 1) SK_DECL(1, 2) SK_DECL(1, 3)
-SK_DECL(2, 0) SK_DECL(2, 1) SK_DECL(2, 2) SK_DECL(2, 3)
 SK_DECL(3, 0) SK_DECL(3, 1) SK_DECL(3, 2) SK_DECL(3, 3)
 SK_DECL(4, 0) SK_DECL(4, 1) SK_DECL(4, 2) SK_DECL(4, 3)
 SK_DECL(5, 0) SK_DECL(5, 1) SK_DECL(5, 2) SK_DECL(5, 3)
@@ -15,12 +13,14 @@ SK_DECL(6, 0) SK_DECL(6, 1) SK_DECL(6, 2) SK_DECL(6, 3)
 SK_DECL(7, 0) SK_DECL(7, 1) SK_DECL(7, 2) SK_DECL(7, 3)
 #undef SK_DECL
 
+void* none_(int, int) { return nullptr; }  // kinds 1 and 2 are not compiled
+
 void* sweep_fn(int kind, int lam, int R, int d) {
   using Pick = void* (*)(int, int);
   static const Pick table[8][4] = {
       {sweep_fn_k0_l0_, sweep_fn_k0_l1_, sweep_fn_k0_l2_, sweep_fn_k0_l3_},
-      {sweep_fn_k1_l0_, sweep_fn_k1_l1_, sweep_fn_k1_l2_, sweep_fn_k1_l3_},
-      {sweep_fn_k2_l0_, sweep_fn_k2_l1_, sweep_fn_k2_l2_, sweep_fn_k2_l3_},
+      {none_, none_, none_, none_},
+      {none_, none_, none_, none_},
       {sweep_fn_k3_l0_, sweep_fn_k3_l1_, sweep_fn_k3_l2_, sweep_fn_k3_l3_},
       {sweep_fn_k4_l0_, sweep_fn_k4_l1_, sweep_fn_k4_l2_, sweep_fn_k4_l3_},
       {sweep_fn_k5_l0_, sweep_fn_k5_l1_, sweep_fn_k5_l2_, sweep_fn_k5_l3_},
@@ -64,11 +64,6 @@ hipError_t launch_sweep(const SweepArgs& a, int lam, int R, int d, hipStream_t s
 hipError_t launch_lifted(const SweepArgs& a, int lam, int R, int d, hipStream_t stream,
                          int waves_per_block) {
   return launch_forward(kKernelLifted, a, lam, R, d, stream, waves_per_block);
-}
-
-hipError_t launch_sweep_store(const SweepArgs& a, int lam, int R, int d, hipStream_t stream,
-                              int waves_per_block) {
-  return launch_forward(kKernelForwardStore, a, lam, R, d, stream, waves_per_block);
 }
 
 }  // namespace sk

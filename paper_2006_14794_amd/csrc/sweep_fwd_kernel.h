@@ -185,7 +185,7 @@ __device__ __forceinline__ bool wave_run(const SweepArgs& a, int64_t w, int lane
 // fine columns of one coarse column), in antidiagonal order so that the S
 // columns form independent dependency chains for the scheduler.
 //   v[r][cc]  out: the block's new values
-//   sv        STORE: the R*S cell sums A + B (row-major)
+//   sv        STORE: the R*S cell sums A + B (row-major, rounded to float)
 //   u[r]      the lane's values at the previous fine column
 //   up[cc]    the row above the strip (from lane l-1) at fine column cc
 //   up_last   the row above at the previous fine column (C of the corner cell)
@@ -218,7 +218,7 @@ __device__ __forceinline__ void cell_block(double (&v)[R][1 << LAM],
 
 // IMPL: the implicit scheme's cell factor (a separate instantiation, so that
 // the explicit kernel carries none of its registers).
-template <int R, int LAM, int D, bool STORE, bool IMPL>
+template <int R, int LAM, int D, bool IMPL>
 __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
   constexpr int DP = (D + 3) & ~3;
   constexpr int S = 1 << LAM;                          // fine columns per coarse column
@@ -275,10 +275,6 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     up[cc] = 1.0;  // lane 0 keeps the boundary value for the whole run
   }
   double up_last = 1.0;
-  // backward support: S = A + B of every cell, per step, groups of four
-  // floats interleaved across the lanes (cell_group_floats)
-  float* __restrict__ sp = nullptr;
-  if constexpr (STORE) sp = a.store + (w - a.wave0) * a.store_stride + (int64_t)lane * 4;
 
   float dyA[DP], dyB[DP], dyC[DP];
   load_row<DP>(yp, dyA);
@@ -315,9 +311,8 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
         for (int c = 0; c < CR; ++c) gk[c] = 1.0 + (double)h32[c];
       }
       double v[R][S];
-      float sv[STORE ? R * S : 1];
-      cell_block<R, LAM, CR, STORE>(v, sv, u, up, up_last, gk);
-      if constexpr (STORE) put_cells<R * S>(sp, sv);
+      float sv[1];
+      cell_block<R, LAM, CR, false>(v, sv, u, up, up_last, gk);
 #pragma unroll
       for (int r = 0; r < R; ++r) u[r] = v[r][S - 1];
 #pragma unroll
@@ -338,7 +333,6 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     }
     ++g;
     yp += DP;
-    if constexpr (STORE) sp += 64 * cell_group_floats(R * S);
   };
 
   for (int32_t t = 0; t < nsteps; t += 3) {

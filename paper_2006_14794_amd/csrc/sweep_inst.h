@@ -1,11 +1,10 @@
-// Instantiations of one sweep kernel (SK_KIND: forward, forward with store,
-// adjoint, persistent pairs, lifted forward, implicit forward, pipelined bands
-// with a fitted top band, pipelined bands of one height) at one dyadic order SK_LAM.  Included by sweep_k{kind}_l{lam}.hip
-// so that the configurations compile in parallel translation units.
+// Instantiations of one sweep kernel (SK_KIND: 0 forward, 3 persistent pairs,
+// 4 lifted forward, 5 implicit forward, 6 pipelined bands with a fitted top
+// band, 7 pipelined bands of one height) at one dyadic order SK_LAM.  Included
+// by sweep_k{kind}_l{lam}.hip so that the configurations compile in parallel
+// translation units.
 #include "dispatch.h"
-#if SK_KIND == 2
-#include "sweep_bwd_kernel.h"
-#elif SK_KIND == 3 || SK_KIND == 6 || SK_KIND == 7
+#if SK_KIND == 3 || SK_KIND == 6 || SK_KIND == 7
 #include "pair_kernel.h"
 #elif SK_KIND == 4
 #include "lifted_kernel.h"
@@ -25,18 +24,7 @@ struct FwdPlain {
   template <int R, int LAM, int D>
   static Fn get() {
     if constexpr (sweep_fits(R, LAM, D))
-      return reinterpret_cast<void*>(&fwd::sweep_kernel<R, LAM, D, false, false>);
-    else
-      return nullptr;
-  }
-};
-#elif SK_KIND == 1
-struct FwdStore {
-  using Fn = void*;
-  template <int R, int LAM, int D>
-  static Fn get() {
-    if constexpr (sweep_fits(R, LAM, D))
-      return reinterpret_cast<void*>(&fwd::sweep_kernel<R, LAM, D, true, false>);
+      return reinterpret_cast<void*>(&fwd::sweep_kernel<R, LAM, D, false>);
     else
       return nullptr;
   }
@@ -72,7 +60,7 @@ struct FwdImplicit {
   template <int R, int LAM, int D>
   static Fn get() {
     if constexpr (sweep_fits(R, LAM, D))
-      return reinterpret_cast<void*>(&fwd::sweep_kernel<R, LAM, D, false, true>);
+      return reinterpret_cast<void*>(&fwd::sweep_kernel<R, LAM, D, true>);
     else
       return nullptr;
   }
@@ -84,17 +72,6 @@ struct Lifted {
   static Fn get() {
     if constexpr (lifted_fits(R, LAM, D))
       return reinterpret_cast<void*>(&lift::lifted_sweep_kernel<R, LAM, D>);
-    else
-      return nullptr;
-  }
-};
-#else
-struct Adjoint {
-  using Fn = void*;
-  template <int R, int LAM, int D>
-  static Fn get() {
-    if constexpr (sweep_fits(R, LAM, D) && adjoint_fits(R, LAM, D))
-      return reinterpret_cast<void*>(&bwd::adjoint_kernel<R, LAM, D>);
     else
       return nullptr;
   }
@@ -118,8 +95,6 @@ void* pick_fixed_lam(int R, int d) {
 
 #if SK_KIND == 0
 void* SK_CAT(SK_CAT(sweep_fn_k0_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<FwdPlain>(R, d); }
-#elif SK_KIND == 1
-void* SK_CAT(SK_CAT(sweep_fn_k1_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<FwdStore>(R, d); }
 #elif SK_KIND == 3
 void* SK_CAT(SK_CAT(sweep_fn_k3_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Pair>(R, d); }
 #elif SK_KIND == 4
@@ -130,8 +105,6 @@ void* SK_CAT(SK_CAT(sweep_fn_k5_l, SK_LAM), _)(int R, int d) { return pick_fixed
 void* SK_CAT(SK_CAT(sweep_fn_k6_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<PairBand>(R, d); }
 #elif SK_KIND == 7
 void* SK_CAT(SK_CAT(sweep_fn_k7_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<PairBand>(R, d); }
-#else
-void* SK_CAT(SK_CAT(sweep_fn_k2_l, SK_LAM), _)(int R, int d) { return pick_fixed_lam<Adjoint>(R, d); }
 #endif
 
 }  // namespace sk

@@ -122,17 +122,29 @@ def test_empty_batches_are_no_ops():
     assert call_pair(paths(n=0), paths(n=0), out=None, ws=None) == _lib.SK_OK
 
 
-def test_unsupported_shapes_are_reported():
-    # the adjoint needs uniform batches and one wave per x path
+def test_gradient_shapes_accepted_and_rejected():
+    # the gradient takes tall x paths (row bands) and ragged batches; beyond 16
+    # channels it is not compiled.  A workspace that is too small is reported
+    # before anything is enqueued (no device memory is touched here).
     lib = _lib.load()
     X = paths(n=2, L=64 * 32 // 8 + 2, d=16)
     Y = paths(n=2, L=8, d=16)
+    need = lib.sigkernel_workspace_bytes(_lib.SK_OP_GRAM_BACKWARD, ctypes.byref(X),
+                                         ctypes.byref(Y), 3, 0)
+    assert need > 0
     st = lib.sigkernel_gram_backward(ctypes.byref(X), ctypes.byref(Y), 3, 0, FAKE, FAKE, FAKE,
-                                     FAKE, 1 << 40, None)
-    assert st == _lib.SK_ERR_UNSUPPORTED
+                                     FAKE, need - 1, None)
+    assert st == _lib.SK_ERR_WORKSPACE
     Xr = paths(n=2, L=16, d=3, off=FAKE)
-    st = lib.sigkernel_gram_backward(ctypes.byref(Xr), ctypes.byref(paths(n=2, L=8, d=3)), 1, 0,
-                                     FAKE, FAKE, FAKE, FAKE, 1 << 40, None)
+    Y3 = paths(n=2, L=8, d=3)
+    need = lib.sigkernel_workspace_bytes(_lib.SK_OP_GRAM_BACKWARD, ctypes.byref(Xr),
+                                         ctypes.byref(Y3), 1, 0)
+    st = lib.sigkernel_gram_backward(ctypes.byref(Xr), ctypes.byref(Y3), 1, 0, FAKE, FAKE, FAKE,
+                                     FAKE, need - 1, None)
+    assert st == _lib.SK_ERR_WORKSPACE
+    X17 = paths(n=2, L=16, d=17)
+    st = lib.sigkernel_gram_backward(ctypes.byref(X17), ctypes.byref(X17), 1, 0, FAKE, FAKE,
+                                     FAKE, FAKE, 1 << 40, None)
     assert st == _lib.SK_ERR_UNSUPPORTED
 
 

@@ -3,9 +3,10 @@ wrappers) against the FP64 oracle's discrete adjoint on the same float32
 inputs.  The oracle's adjoint is itself pinned by central finite differences
 of the oracle forward (tests/test_oracle_pins.py).
 
-Tolerance: |g_gpu - g_ref| <= 2e-5 max|g_ref| per gradient tensor (the GPU
-forms increments, their inner products and the increment-gradient
-contractions in float32; the sweep and its adjoint run in double).
+Bar (conftest.grad_close): |g_gpu - g_ref| <= 1e-5 max|g_ref| for every
+component, and relative error <= 1e-4 on every component above 1e-3
+max|g_ref|.  The GPU forms increments and their inner products in float32;
+the sweep, its adjoint and every gradient sum run in double.
 """
 import numpy as np
 import pytest
@@ -14,22 +15,18 @@ import torch
 import oracle
 import paper_2006_14794_amd as sk
 import workloads
+from conftest import grad_close
+from paper_2006_14794_amd import RaggedPaths
 
 pytestmark = pytest.mark.gpu
-
-RTOL = 2e-5
 
 
 def cuda(a):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).cuda()
 
 
-def close(got, ref, rtol=RTOL):
-    got = np.asarray(got, dtype=np.float64)
-    scale = max(np.abs(ref).max(), 1e-30)
-    err = np.abs(got - ref).max() / scale
-    assert err <= rtol, err
-    return err
+def close(got, ref, name="grad"):
+    return grad_close(got, ref, name)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -48,8 +45,8 @@ def test_gram_backward_matches_oracle_adjoint(lam, d):
     gx, gy = sk.sigkernel_gram_backward(cuda(X), cuda(Y), cuda(dK), lam)
     rx, ry = oracle.gram_backward(X.astype(np.float64), Y.astype(np.float64),
                                   dK.astype(np.float64), lam)
-    close(gx.cpu().numpy(), rx)
-    close(gy.cpu().numpy(), ry)
+    close(gx.cpu().numpy(), rx, f"dX lam{lam} d{d}")
+    close(gy.cpu().numpy(), ry, f"dY lam{lam} d{d}")
 
 
 @pytest.mark.parametrize("run", [1, 2, 3, 7])
@@ -60,8 +57,8 @@ def test_gram_backward_streamed_runs(run, monkeypatch):
     gx, gy = sk.sigkernel_gram_backward(cuda(X), cuda(Y), cuda(dK), 1)
     rx, ry = oracle.gram_backward(X.astype(np.float64), Y.astype(np.float64),
                                   dK.astype(np.float64), 1)
-    close(gx.cpu().numpy(), rx)
-    close(gy.cpu().numpy(), ry)
+    close(gx.cpu().numpy(), rx, f"dX run{run}")
+    close(gy.cpu().numpy(), ry, f"dY run{run}")
 
 
 @pytest.mark.parametrize("no_diag", [False, True])
@@ -77,7 +74,7 @@ def test_symmetric_gram_backward(no_diag, run, monkeypatch):
     if no_diag:
         np.fill_diagonal(w, 0.0)
     rx, ry = oracle.gram_backward(X.astype(np.float64), X.astype(np.float64), w, 2)
-    close(gx.cpu().numpy(), rx + ry)
+    close(gx.cpu().numpy(), rx + ry, f"dX symmetric run{run} no_diag={no_diag}")
 
 
 def test_autograd_gram_and_symmetric():
@@ -132,5 +129,70 @@ def test_mmd_workload_full_size_sampled_pairs():
     gx, gy = sk.sigkernel_gram_backward(cuda(X), cuda(Y), cuda(dK), 1)
     rx, ry = oracle.gram_backward(X.astype(np.float64), Y.astype(np.float64),
                                   dK.astype(np.float64), 1)
-    close(gx.cpu().numpy(), rx)
-    close(gy.cpu().numpy(), ry)
+    close(gx.cpu().numpy(), rx, "dX full MMD shape")
+    close(gy.cpu().numpy(), ry, "dY full MMD shape")
+
+
+@pytest.mark.parametrize("lx,lam", [(514, 1), (1500, 1), (130, 3), (700, 0)])
+def test_tall_x_paths_swept_in_bands(lx, lam):
+    # x paths taller than one band of 256 fine rows: 1026 .. 2998 rows at order
+    # 1 (5 and 12 bands), 1032 at order 3, 699 at order 0
+    X = workloads.random_paths(910 + lx, 2, lx, 3, std=0.3 / np.sqrt(lx))
+    Y = workloads.random_paths(911 + lx, 3, 37, 3, std=0.3 / 6)
+    dK = np.random.default_rng(lx).normal(size=(2, 3)).astype(np.float32)
+    gx, gy = sk.sigkernel_gram_backward(cuda(X), cuda(Y), cuda(dK), lam)
+    rx, ry = oracle.gram_backward(X.astype(np.float64), Y.astype(np.float64),
+                                  dK.astype(np.float64), lam)
+    close(gx.cpu().numpy(), rx, f"dX tall {lx} lam{lam}")
+    close(gy.cpu().numpy(), ry, f"dY tall {lx} lam{lam}")
+
+
+def _ragged(seed, lens, d):
+    return [workloads.random_paths(seed + i, 1, L, d, std=0.3 / np.sqrt(max(L - 1, 1)))[0]
+            for i, L in enumerate(lens)]
+
+
+@pytest.mark.parametrize("lam", [1, 2])
+def test_ragged_gram_backward(lam):
+    # uneven lengths, one-point paths among them, an x path needing two bands
+    xs = _ragged(920, [1, 17, 300, 2, 64, 5], 4)
+    ys = _ragged(940, [33, 1, 9, 130, 2], 4)
+    X, Y = RaggedPaths.from_list(xs, "cuda"), RaggedPaths.from_list(ys, "cuda")
+    dK = np.random.default_rng(lam).normal(size=(6, 5)).astype(np.float32)
+    gx, gy = sk.sigkernel_gram_backward(X, Y, cuda(dK), lam)
+    rx, ry = oracle.gram_backward([x.astype(np.float64) for x in xs],
+                                  [y.astype(np.float64) for y in ys], dK.astype(np.float64), lam)
+    assert gx.shape == (sum(len(x) for x in xs), 4)
+    close(gx.cpu().numpy(), rx, f"dX ragged lam{lam}")
+    close(gy.cpu().numpy(), ry, f"dY ragged lam{lam}")
+    # the one-point paths have zero gradient
+    assert not gx[0].abs().any() and not gy[33].abs().any()
+
+
+@pytest.mark.parametrize("no_diag", [False, True])
+def test_ragged_symmetric_gram_backward(no_diag):
+    xs = _ragged(960, [12, 1, 40, 7, 260], 3)
+    X = RaggedPaths.from_list(xs, "cuda")
+    dK = np.random.default_rng(6).normal(size=(5, 5)).astype(np.float32)
+    gx, gy = sk.sigkernel_gram_backward(X, None, cuda(dK), 1, symmetric=True, no_diag=no_diag)
+    assert gy is None
+    w = dK.astype(np.float64).copy()
+    if no_diag:
+        np.fill_diagonal(w, 0.0)
+    xd = [x.astype(np.float64) for x in xs]
+    rx, ry = oracle.gram_backward(xd, xd, w, 1)
+    close(gx.cpu().numpy(), rx + ry, f"dX ragged symmetric no_diag={no_diag}")
+
+
+def test_ragged_broken_path_gives_nan_gradient_for_its_pairs():
+    xs = _ragged(980, [10, 30, 12], 3)
+    ys = _ragged(990, [11, 9], 3)
+    X = RaggedPaths.from_list(xs, "cuda")
+    X.max_len = 20  # path 1 breaks the declared bound
+    Y = RaggedPaths.from_list(ys, "cuda")
+    dK = torch.ones((3, 2), device="cuda")
+    gx, gy = sk.sigkernel_gram_backward(X, Y, dK, 1)
+    gx = gx.cpu().numpy()
+    assert np.all(np.isnan(gx[10:40]))  # the broken path's rows
+    assert np.all(np.isfinite(gx[:10])) and np.all(np.isfinite(gx[40:]))
+    assert np.all(np.isnan(gy.cpu().numpy()))  # every y path meets the broken one
