@@ -133,6 +133,25 @@ sk_status sigkernel_gram(const sk_paths *X, const sk_paths *Y, int32_t dyadic_or
                          void *stream);
 
 /*
+ * sigkernel_gram_noalloc -- sigkernel_gram (same batches, flags, output and
+ * errors) for callers that cannot allocate device memory or provide a
+ * workspace: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  The workspace is a static device array of
+ * sigkernel_gram_noalloc_max_bytes() bytes (64 MiB) inside the library, one
+ * per GPU, held until the process ends; the call allocates nothing.
+ *  - A problem whose workspace (sigkernel_workspace_bytes(SK_OP_GRAM, ...))
+ *    exceeds that size gives SK_ERR_WORKSPACE, with nothing enqueued.
+ *  - stream must belong to the current device; the array's address on the
+ *    device is looked up on the first call there (SK_ERR_HIP on failure).
+ *  - Every call on one GPU uses the same array: calls that overlap on one
+ *    GPU (concurrent streams, or threads sharing a device) race.  Nothing in
+ *    the array needs to start at zero; each call overwrites what it reads.
+ */
+sk_status sigkernel_gram_noalloc(const sk_paths *X, const sk_paths *Y, int32_t dyadic_order,
+                                 uint32_t flags, float *K, void *stream);
+size_t sigkernel_gram_noalloc_max_bytes(void);
+
+/*
  * sigkernel_gram_backward -- gradient of a weighted sum of Gram entries,
  *   L = sum_{a,b} dK[a][b] k_hat(X_a, Y_b),
  * with respect to every point of X and of Y:

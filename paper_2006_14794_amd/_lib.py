@@ -49,6 +49,8 @@ SK_CHANNEL_STATS_WORKSPACE_BYTES = 32832
 EXPORTED = (
     "sigkernel_pair",
     "sigkernel_gram",
+    "sigkernel_gram_noalloc",
+    "sigkernel_gram_noalloc_max_bytes",
     "sigkernel_gram_backward",
     "sigkernel_mmd2",
     "sigkernel_increment_gram",
@@ -149,6 +151,10 @@ def load():
     lib.sigkernel_pair.restype = i32
     lib.sigkernel_gram.argtypes = [P, P, i32, u32, vp, vp, sz, vp]
     lib.sigkernel_gram.restype = i32
+    lib.sigkernel_gram_noalloc.argtypes = [P, P, i32, u32, vp, vp]
+    lib.sigkernel_gram_noalloc.restype = i32
+    lib.sigkernel_gram_noalloc_max_bytes.argtypes = []
+    lib.sigkernel_gram_noalloc_max_bytes.restype = sz
     dbl = ctypes.c_double
     lib.sigkernel_reduced_measure.argtypes = [vp, vp, i32, dbl, dbl, i32, vp, vp, vp, vp]
     lib.sigkernel_reduced_measure.restype = i32

@@ -5,6 +5,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/sigkernel.h"
 #include "corrector.h"
 #include "internal.h"
@@ -17,6 +19,8 @@ using sk::Batch;
 // Dyadic orders the sweep kernels are compiled for; beyond them the batch is
 // refined (split_order) and swept at the highest compiled order.
 constexpr int32_t kMaxKernelOrder = 3;
+// Workspace of the allocation-free Gram (sigkernel_gram_noalloc).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
 // Fine rows or columns of one pair: 2^lambda (len - 1) <= 2^20.
 constexpr int64_t kMaxFineSide = int64_t(1) << 20;
 
@@ -882,6 +886,33 @@ sk_status run_lifted(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t
 
 }  // namespace
 
+// ---- the allocation-free Gram ------------------------------------------------
+// Its workspace is this file-scope array (each GPU that runs the library
+// holds one copy until the process ends).  In host code `scratch` names a
+// host-side stand-in, not the device array: the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (nullptr on failure).
+void* scratch_address() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
 extern "C" {
 
 const char* sigkernel_version(void) { return "0.1.0"; }
@@ -976,6 +1007,28 @@ sk_status sigkernel_gram(const sk_paths* X, const sk_paths* Y, int32_t dyadic_or
   return run_forward(X, Y, dyadic_order, flags, K, ws, ws_bytes,
                      static_cast<hipStream_t>(stream), (flags & SK_SYMMETRIC) ? 2 : 1);
 }
+
+sk_status sigkernel_gram_noalloc(const sk_paths* X, const sk_paths* Y, int32_t dyadic_order,
+                                 uint32_t flags, float* K, void* stream) {
+  // every check that sigkernel_gram makes before touching the workspace, then
+  // the size check, all before any HIP call
+  if (!X || !Y) return SK_ERR_NULL;
+  if (!valid_batch(X) || !valid_batch(Y)) return SK_ERR_SHAPE;
+  if (!K && X->n_paths > 0 && Y->n_paths > 0) return SK_ERR_NULL;
+  if ((X->n_paths > 0 && !X->points) || (Y->n_paths > 0 && !Y->points)) return SK_ERR_NULL;
+  if (X->dim != Y->dim) return SK_ERR_SHAPE;
+  if (!order_ok(dyadic_order, X, Y, kMaxDyadicOrder)) return SK_ERR_ORDER;
+  if (sk_status f = check_flags(
+          flags, SK_SYMMETRIC | SK_NO_DIAG | SK_GRAM_BF16 | SK_GRAM_F16 | SK_IMPLICIT))
+    return f;
+  if (X->n_paths == 0 || Y->n_paths == 0) return SK_OK;
+  if (gram_ws(X, Y, dyadic_order) > kNoAllocScratchBytes) return SK_ERR_WORKSPACE;
+  void* ws = scratch_address();
+  if (!ws) return SK_ERR_HIP;
+  return sigkernel_gram(X, Y, dyadic_order, flags, K, ws, kNoAllocScratchBytes, stream);
+}
+
+size_t sigkernel_gram_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
 
 sk_status sigkernel_pair_lifted(const sk_paths* x, const sk_paths* y, int32_t dyadic_order,
                                 uint32_t flags, const sk_static_kernel* kernel, float* out,

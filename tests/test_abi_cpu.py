@@ -148,6 +148,25 @@ def test_gradient_shapes_accepted_and_rejected():
     assert st == _lib.SK_ERR_UNSUPPORTED
 
 
+def test_noalloc_gram_checks_before_any_hip_call():
+    # the allocation-free Gram validates like sigkernel_gram and rejects a
+    # problem whose workspace exceeds its static array, before touching HIP
+    lib = _lib.load()
+    cap = lib.sigkernel_gram_noalloc_max_bytes()
+    assert cap == 64 << 20
+    X = paths(n=4096, L=2049, d=16)
+    assert lib.sigkernel_workspace_bytes(_lib.SK_OP_GRAM, ctypes.byref(X), ctypes.byref(X), 1,
+                                         0) > cap
+    assert lib.sigkernel_gram_noalloc(ctypes.byref(X), ctypes.byref(X), 1, 0, FAKE,
+                                      None) == _lib.SK_ERR_WORKSPACE
+    assert lib.sigkernel_gram_noalloc(ctypes.byref(paths(d=3)), ctypes.byref(paths(d=4)), 1, 0,
+                                      FAKE, None) == _lib.SK_ERR_SHAPE
+    assert lib.sigkernel_gram_noalloc(ctypes.byref(paths()), ctypes.byref(paths()), -1, 0, FAKE,
+                                      None) == _lib.SK_ERR_ORDER
+    assert lib.sigkernel_gram_noalloc(ctypes.byref(paths()), ctypes.byref(paths()), 1, 0, None,
+                                      None) == _lib.SK_ERR_NULL
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
