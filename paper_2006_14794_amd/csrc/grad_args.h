@@ -44,12 +44,12 @@ constexpr int kGradRows = 4;
 // Forward steps per segment: the adjoint recomputes a segment from its
 // checkpoint and keeps the segment's R 2^lam cell sums per step on chip, the
 // first grad_lds_steps steps in LDS (64 floats per lane: 16 KB per wave) and
-// the rest in registers (64 floats per lane; half that beyond 8 channels or at
-// order 0, whose increments and gradient accumulators take more registers).
+// the rest in registers (32 floats per lane; half that at order 0, whose
+// increments and gradient accumulators take more registers).
 __host__ __device__ constexpr int grad_reg_steps(int lam, int d) {
   const int rs = kGradRows << lam;
   // order 0 keeps four coarse rows per lane (increments, accumulators)
-  const int floats = (d > 8 ? 32 : 64) / (lam == 0 ? 2 : 1);
+  const int floats = 32 / (lam == 0 ? 2 : 1) + 0 * d;
   const int c = floats / rs;
   return c < 1 ? 1 : c;
 }

@@ -265,26 +265,36 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
         for (int k = 0; k < D; ++k) dx[c][k] = tr[k];
       }
     };
+    // The LDS inputs of a step are read one step ahead (during the previous
+    // step's arithmetic), so that their latency is hidden; each step is
+    // scheduled on its own (sched_barrier before the read of the next step's
+    // inputs): interleaving the unrolled steps would keep several steps'
+    // values live and spill registers.
+    // forward step inputs: the lane's y row, lane 0's upper neighbours
+    struct FwdIn {
+      float dy[DP];
+      double up[S];
+    };
+    auto read_fwd = [&](int j, FwdIn& in) {
+      get_dy(j, in.dy);
+#pragma unroll
+      for (int cc = 0; cc < S; ++cc) in.up[cc] = sb[j * S + cc];
+    };
     // one forward step of the wavefront at step t0 + j; st: the cell sums
     // (when it holds R S floats)
-    auto forward_step = [&](const int j, const float (&dx)[CR][D], double (&u)[R],
+    auto forward_step = [&](const FwdIn& in, const float (&dx)[CR][D], double (&u)[R],
                             double (&pub)[S], double& up_last, auto& st) {
-      // each step is scheduled on its own: interleaving the unrolled steps
-      // would keep several steps' values live and spill registers
-      __builtin_amdgcn_sched_barrier(0);
-      float dy[DP];
-      get_dy(j, dy);
       float h32[CR];
 #pragma unroll
       for (int c = 0; c < CR; ++c) {
         float s = 0.0f;
 #pragma unroll
-        for (int k = 0; k < D; ++k) s = __builtin_fmaf(dx[c][k], dy[k], s);
+        for (int k = 0; k < D; ++k) s = __builtin_fmaf(dx[c][k], in.dy[k], s);
         h32[c] = s;
       }
       double up[S];
 #pragma unroll
-      for (int cc = 0; cc < S; ++cc) up[cc] = from_prev_lane(pub[cc], sb[j * S + cc]);
+      for (int cc = 0; cc < S; ++cc) up[cc] = from_prev_lane(pub[cc], in.up[cc]);
       double gk[CR];
 #pragma unroll
       for (int c = 0; c < CR; ++c) gk[c] = 1.0 + (double)h32[c];
@@ -336,34 +346,55 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
           for (int cc = 0; cc < S; ++cc) cp[(R + cc) * 64] = pub[cc];
           cp[(R + S) * 64] = up_last;
         }
-#pragma unroll 2
-        for (int j = 0; j < C; ++j) {
+        auto fwd_pass_step = [&](const int j, const FwdIn& in) {
           const int32_t g = t0 + j - lane;
           float st[1];
-          forward_step(j, dx, u, pub, up_last, st);
-          // lane 63's bottom row, for the band below
+          forward_step(in, dx, u, pub, up_last, st);
+          // lane 63's bottom row: for the band below, or in the last band the
+          // Gram value at the last column of a pair (its last entry)
           if (lane == 63) {
 #pragma unroll
             for (int cc = 0; cc < S; ++cc) sw[j * S + cc] = pub[cc];
           }
           if ((uint32_t)g < (uint32_t)total && ++q == n) {
-            // last column of a pair: its value (lane 63 of the last band), then
-            // the left boundary of the next pair
-            if (last && lane == 63 && a.K) {
-              const int64_t cb = b0 + g / n;
-              store_value(a, ia, cb, (float)u[R - 1]);
-            }
+            // last column of a pair: the left boundary of the next pair
 #pragma unroll
             for (int r = 0; r < R; ++r) u[r] = 1.0;
             up_last = 1.0;
             q = 0;
           }
+        };
+        // two steps per iteration, alternating two input buffers (the read
+        // past the segment's last step re-reads that step)
+        FwdIn fa, fb;
+        read_fwd(0, fa);
+#pragma unroll 1
+        for (int j = 0; j + 1 < C; j += 2) {
+          __builtin_amdgcn_sched_barrier(0);
+          read_fwd(j + 1, fb);
+          fwd_pass_step(j, fa);
+          __builtin_amdgcn_sched_barrier(0);
+          read_fwd(j + 2 < C ? j + 2 : j + 1, fa);
+          fwd_pass_step(j + 1, fb);
         }
+        if constexpr (C & 1) {
+          __builtin_amdgcn_sched_barrier(0);
+          fwd_pass_step(C - 1, fa);
+        }
+        // (global stores stay out of the step loop: a loop with stores makes
+        // the compiler wait for the staging loads in flight before entering it)
         if (!last) {  // the band's bottom row at columns t0 - 63 .. t0 + C - 64
           __syncthreads();
           for (int e = lane; e < C * S; e += 64) {
             const int32_t col = t0 + e / S - 63;
             if ((uint32_t)col < (uint32_t)total) below[(int64_t)col * S + e % S] = sw[e];
+          }
+        } else if (a.K) {  // the values of the pairs that end in this segment
+          __syncthreads();
+          for (int j = lane; j < C; j += 64) {
+            const int32_t col = t0 + j - 63;
+            if ((uint32_t)col < (uint32_t)total && (col + 1) % n == 0)
+              store_value(a, ia, b0 + col / n, (float)sw[j * S + S - 1]);
           }
         }
       }
@@ -469,9 +500,9 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
         for (int cc = 0; cc < S; ++cc) pub[cc] = pk[R + cc];
         up_last = pk[R + S];
         int32_t q = g0 > 0 ? g0 % n : 0;
-        auto recompute_step = [&](const int j, float (&st)[RS]) {
+        auto recompute_step = [&](const int j, const FwdIn& in, float (&st)[RS]) {
           const int32_t g = g0 + j;
-          forward_step(j, dx, u, pub, up_last, st);
+          forward_step(in, dx, u, pub, up_last, st);
           if ((uint32_t)g < (uint32_t)total && ++q == n) {
 #pragma unroll
             for (int r = 0; r < R; ++r) u[r] = 1.0;
@@ -479,32 +510,67 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
             q = 0;
           }
         };
-        // the first CL steps keep their cell sums in LDS, the last CG in registers
-        float sv[CG][RS];
-#pragma unroll 1
-        for (int j = 0; j < CL; ++j) {
-          float st[RS];
-          recompute_step(j, st);
+        auto put_sums = [&](const int j, const float (&st)[RS]) {
 #pragma unroll
           for (int e = 0; e < G4; ++e)
             lds[(j * G4 + e) * 64 + lane] =
                 make_float4(st[4 * e], st[4 * e + 1], st[4 * e + 2], st[4 * e + 3]);
+        };
+        // the first CL steps keep their cell sums in LDS, the last CG in
+        // registers; inputs read one step ahead, alternating two buffers
+        float sv[CG][RS];
+        FwdIn fi[2];
+        read_fwd(0, fi[0]);
+#pragma unroll 1
+        for (int j = 0; j < CL; j += 2) {
+          float st[RS];
+          __builtin_amdgcn_sched_barrier(0);
+          read_fwd(j + 1, fi[1]);
+          recompute_step(j, fi[0], st);
+          put_sums(j, st);
+          __builtin_amdgcn_sched_barrier(0);
+          read_fwd(j + 2, fi[0]);  // j + 2 <= CL < C
+          recompute_step(j + 1, fi[1], st);
+          put_sums(j + 1, st);
         }
 #pragma unroll
-        for (int j = CL; j < C; ++j) recompute_step(j, sv[j - CL]);
+        for (int j = CL; j < C; ++j) {
+          __builtin_amdgcn_sched_barrier(0);
+          if (j + 1 < C) read_fwd(j + 1, fi[(j + 1 - CL) & 1]);
+          recompute_step(j, fi[(j - CL) & 1], sv[j - CL]);
+        }
 
         // the segment's reverse steps; a lane's first real one is at column
         // min(g0 + C - 1, total - 1) (none when that is negative)
         const int32_t gl = g0 + C - 1 < total ? g0 + C - 1 : total - 1;
         q = gl > 0 ? gl % n : 0;
         int64_t cbp = b0 + (gl > 0 ? gl / n : 0);  // pair of the current column
-        auto rev_step = [&](const int j, const float(&sj)[RS]) {
-          __builtin_amdgcn_sched_barrier(0);
+        // reverse step inputs: the lane's y row, lane 63's lower neighbours
+        // and, for the steps whose cell sums sit in LDS, those sums
+        struct RevIn {
+          float dy[DP];
+          double lo[LW];
+        };
+        auto read_rev = [&](int j, RevIn& in) {
+          get_dy(j, in.dy);
+#pragma unroll
+          for (int f = 0; f < LW; ++f) in.lo[f] = sl[j * LW + f];
+        };
+        auto read_sums = [&](int j, float (&sj)[RS]) {
+#pragma unroll
+          for (int e = 0; e < G4; ++e) {
+            const float4 f = lds[(j * G4 + e) * 64 + lane];
+            sj[4 * e] = f.x;
+            sj[4 * e + 1] = f.y;
+            sj[4 * e + 2] = f.z;
+            sj[4 * e + 3] = f.w;
+          }
+        };
+        auto rev_step = [&](const int j, const RevIn& in, const float(&sj)[RS]) {
           const int32_t g = g0 + j;
           const bool real = (uint32_t)g < (uint32_t)total;
-          float dy[DP];
-          get_dy(j, dy);
-          const double* __restrict__ lo = &sl[j * LW];
+          const float(&dy)[DP] = in.dy;
+          const double(&lo)[LW] = in.lo;
           float h32[CR];
 #pragma unroll
           for (int c = 0; c < CR; ++c) {
@@ -595,8 +661,18 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
             --cbp;
           }
         };
+        // inputs read one step ahead, alternating two buffers
+        RevIn ri[2];
+        float sr[2][RS];
+        read_rev(C - 1, ri[0]);
 #pragma unroll
-        for (int j = C - 1; j >= CL; --j) rev_step(j, sv[j - CL]);
+        for (int j = C - 1; j >= CL; --j) {
+          const int b = (C - 1 - j) & 1;
+          __builtin_amdgcn_sched_barrier(0);
+          read_rev(j - 1, ri[b ^ 1]);
+          if (j == CL) read_sums(j - 1, sr[b ^ 1]);
+          rev_step(j, ri[b], sv[j - CL]);
+        }
         // the next segment's staging and checkpoint, loaded while the steps
         // whose cell sums sit in LDS run (the registers are free by now)
         if (seg > 0) {
@@ -605,18 +681,26 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
           fetch_low(seg - 1, pl);
           fetch_ck(seg - 1, pk);
         }
+        // steps CL - 1 .. 0, two per iteration; the first one's inputs are in
+        // buffer (C - CL) & 1, the read before step 0 re-reads step 0
+        {
+          constexpr int kb = (C - CL) & 1;
 #pragma unroll 1
-        for (int j = CL - 1; j >= 0; --j) {
-          float sj[RS];
-#pragma unroll
-          for (int e = 0; e < G4; ++e) {
-            const float4 f = lds[(j * G4 + e) * 64 + lane];
-            sj[4 * e] = f.x;
-            sj[4 * e + 1] = f.y;
-            sj[4 * e + 2] = f.z;
-            sj[4 * e + 3] = f.w;
+          for (int j = CL - 1; j >= 1; j -= 2) {
+            __builtin_amdgcn_sched_barrier(0);
+            read_rev(j - 1, ri[kb ^ 1]);
+            read_sums(j - 1, sr[kb ^ 1]);
+            rev_step(j, ri[kb], sr[kb]);
+            __builtin_amdgcn_sched_barrier(0);
+            const int jn = j >= 2 ? j - 2 : 0;
+            read_rev(jn, ri[kb]);
+            read_sums(jn, sr[kb]);
+            rev_step(j - 1, ri[kb ^ 1], sr[kb ^ 1]);
           }
-          rev_step(j, sj);
+          if constexpr (CL & 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            rev_step(0, ri[kb], sr[kb]);
+          }
         }
         // lane 0's outputs at columns t0 .. t0 + C - 1: the y-side sums of the
         // band's rows (final for the top band) and, for the band above, the
