@@ -1245,6 +1245,13 @@ static sk_status gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dya
   }
   if (!sk::grad_supported(lam, d)) return SK_ERR_UNSUPPORTED;
   const GradPlan P = grad_plan(X, Y, dyadic_order, flags);
+  // the kernel addresses a task's scratch slot, y rows and y-side sums with
+  // 32-bit byte offsets
+  const uint64_t k4G = 1ull << 32;
+  if ((uint64_t)P.slot_stride * sizeof(double) >= k4G ||
+      (uint64_t)P.cols_max * sk::padded_dim(d) * sizeof(float) >= k4G ||
+      (uint64_t)P.cols_max * d * sizeof(double) >= k4G)
+    return SK_ERR_UNSUPPORTED;
   if (!ws) return SK_ERR_WORKSPACE;
   if (ws_bytes < P.total) return SK_ERR_WORKSPACE;
 
@@ -1319,10 +1326,13 @@ static sk_status gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dya
   ga.nseg_max = P.nseg_max;
   ga.cols_max = P.cols_max;
   ga.part_x = reinterpret_cast<double*>(base + P.partx);
-  ga.part_y = reinterpret_cast<double*>(base + P.party);
+  // the y-side sums only when a y gradient is asked for (the y batch's, or
+  // the second argument of a symmetric Gram's pairs)
+  const bool ys = sym || dY != nullptr;
+  ga.part_y = ys ? reinterpret_cast<double*>(base + P.party) : nullptr;
   ga.mrows = P.mrows;
   ga.nrows = P.nrows;
-  if (sk::launch_grad(ga, lam, d, P.slots, st) != hipSuccess) return SK_ERR_HIP;
+  if (sk::launch_grad(ga, lam, d, ys, P.slots, st) != hipSuccess) return SK_ERR_HIP;
 
   // the parts of a refined increment are the increment over rep: their
   // gradients sum, times 1 / rep, to the increment's

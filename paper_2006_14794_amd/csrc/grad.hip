@@ -4,17 +4,17 @@
 
 namespace sk {
 
-void* grad_fn_l0_(int d);
-void* grad_fn_l1_(int d);
-void* grad_fn_l2_(int d);
-void* grad_fn_l3_(int d);
+void* grad_fn_l0_(int d, bool ys);
+void* grad_fn_l1_(int d, bool ys);
+void* grad_fn_l2_(int d, bool ys);
+void* grad_fn_l3_(int d, bool ys);
 
-void* grad_fn(int lam, int d) {
+void* grad_fn(int lam, int d, bool ys) {
   switch (lam) {
-    case 0: return grad_fn_l0_(d);
-    case 1: return grad_fn_l1_(d);
-    case 2: return grad_fn_l2_(d);
-    case 3: return grad_fn_l3_(d);
+    case 0: return grad_fn_l0_(d, ys);
+    case 1: return grad_fn_l1_(d, ys);
+    case 2: return grad_fn_l2_(d, ys);
+    case 3: return grad_fn_l3_(d, ys);
     default: return nullptr;
   }
 }
@@ -85,10 +85,11 @@ __global__ __launch_bounds__(256) void grad_points_kernel(const GradPointArgs a)
 
 }  // namespace
 
-bool grad_supported(int lam, int d) { return grad_fn(lam, d) != nullptr; }
+bool grad_supported(int lam, int d) { return grad_fn(lam, d, true) != nullptr; }
 
-hipError_t launch_grad(const GradArgs& a, int lam, int d, int64_t slots, hipStream_t stream) {
-  auto f = reinterpret_cast<void (*)(const GradArgs)>(grad_fn(lam, d));
+hipError_t launch_grad(const GradArgs& a, int lam, int d, bool ys, int64_t slots,
+                       hipStream_t stream) {
+  auto f = reinterpret_cast<void (*)(const GradArgs)>(grad_fn(lam, d, ys));
   if (!f) return hipErrorInvalidValue;
   if (a.n_tasks <= 0 || slots <= 0) return hipSuccess;
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, stream, a.counter, 1);

@@ -50,6 +50,8 @@
 #pragma once
 #include <math.h>
 
+#include <type_traits>
+
 #include "grad_args.h"
 #include "sweep_fwd_kernel.h"
 
@@ -78,6 +80,15 @@ __device__ __forceinline__ double from_next_lane(double v, double keep) {
                                           (unsigned long long)(unsigned)lo));
 }
 
+// base[i] with a 32-bit byte offset (a uniform base and one offset register:
+// the addressing of the staging loads and stores of a task, whose buffers are
+// far below 4 GB)
+template <class T>
+__device__ __forceinline__ T& at(T* base, uint32_t i) {
+  using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return *reinterpret_cast<T*>(reinterpret_cast<C*>(base) + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+
 // Upstream weight of the solve (x_ia, y_b): in the upper triangle of a
 // symmetric Gram, K[a][b] and K[b][a] are one solve.
 __device__ __forceinline__ double pair_weight(const GradArgs& a, int64_t ia, int64_t b) {
@@ -103,11 +114,15 @@ __device__ __forceinline__ void fill_rows(double* __restrict__ p, int64_t n, dou
 // Two waves per SIMD (at most 256 registers) up to 4 channels below order 3;
 // otherwise one or two, as the registers allow: wider increments and
 // accumulators, or the eight fine columns of order 3, would spill to memory.
-template <int R, int LAM, int D, int CL, int CG>
+// YS: the y-side gradients are formed (the gradient of the y batch, or of a
+// symmetric Gram); without them the kernel forms the x side only.
+template <int R, int LAM, int D, int CL, int CG, bool YS>
 __global__ __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_kernel(
     const GradArgs a) {
   constexpr int DP = (D + 3) & ~3;
+  constexpr int DY = YS ? D : 0;          // y-side sums per column
+  constexpr int DYA = YS ? D : 1;         // (their array extent)
   constexpr int S = 1 << LAM;
   constexpr int CR = (R >> LAM) > 0 ? (R >> LAM) : 1;
   constexpr int RS = R * S;
@@ -118,7 +133,7 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
   constexpr int PY = (Y4 + 63) / 64;      // ... per lane
   constexpr int NB = C * S;               // lane 0's upper neighbours per segment
   constexpr int PB = (NB + 63) / 64;
-  constexpr int LW = S + 1 + D;           // a band's hand-over per column: S a values,
+  constexpr int LW = S + 1 + DY;          // a band's hand-over per column: S a values,
                                           // one coefficient, D y-side sums
   constexpr int NL = C * LW;              // lane 63's lower neighbours per segment
   constexpr int PL = (NL + 63) / 64;
@@ -166,13 +181,14 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
     if (a.mode == 2 && a.no_diag && b0 == ia && b0 < b1) {
       // the diagonal of a symmetric Gram without it: the constant 0, no
       // gradient (every lane stores the same values)
-      fill_rows(a.part_y + ((int64_t)ia * a.ny + ia) * a.nrows * D, (int64_t)a.nrows * D,
-                m < 0 ? __builtin_nan("") : 0.0, lane);
+      if (YS)
+        fill_rows(a.part_y + ((int64_t)ia * a.ny + ia) * a.nrows * D, (int64_t)a.nrows * D,
+                  m < 0 ? __builtin_nan("") : 0.0, lane);
       if (a.K) a.K[ia * a.ny + ia] = 0.0f;
       ++b0;
     }
     const int32_t n = b0 < b1 ? n_inc(a.y_n, a.y_len, b0) : 0;
-    double* __restrict__ pyt = a.part_y + ((int64_t)ia * a.ny + b0) * a.nrows * D;
+    double* __restrict__ pyt = YS ? a.part_y + ((int64_t)ia * a.ny + b0) * a.nrows * D : nullptr;
 
     if (!(b0 < b1 && m > 0 && n > 0)) {
       // Nothing to sweep.  Values: a broken path NaN, a one-point path 1;
@@ -182,8 +198,9 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
       for (int64_t b = b0; b < b1; ++b) {
         const int32_t nb_ = n_inc(a.y_n, a.y_len, b);
         const bool bad = m < 0 || nb_ < 0;
-        fill_rows(a.part_y + ((int64_t)ia * a.ny + b) * a.nrows * D, (int64_t)a.nrows * D,
-                  bad ? __builtin_nan("") : 0.0, lane);
+        if (YS)
+          fill_rows(a.part_y + ((int64_t)ia * a.ny + b) * a.nrows * D, (int64_t)a.nrows * D,
+                    bad ? __builtin_nan("") : 0.0, lane);
         if (a.K) store_value(a, ia, b, bad ? __builtin_nanf("") : 1.0f);
       }
       continue;
@@ -206,7 +223,7 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
         py[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         const int32_t g = t0 - 63 + e / (DP / 4);
         if (e < Y4 && (uint32_t)g < (uint32_t)total)
-          py[i] = *reinterpret_cast<const float4*>(ycol + (int64_t)g * DP + (e % (DP / 4)) * 4);
+          py[i] = at(reinterpret_cast<const float4*>(ycol), (uint32_t)(g * (DP / 4) + e % (DP / 4)));
       }
     };
     auto put_y = [&](const float4 (&py)[PY]) {
@@ -228,7 +245,7 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
         if (!top && e < NB) {
           int32_t col = t0 + e / S;
           col = col < total ? col : total - 1;
-          pb[i] = above[(int64_t)col * S + e % S];
+          pb[i] = at(above, (uint32_t)(col * S + e % S));
         }
       }
     };
@@ -317,7 +334,7 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
       load_dx(p0, dx);
       const double* __restrict__ above = hand_f + (int64_t)(band > 0 ? band - 1 : 0) * hf_band;
       double* __restrict__ below = hand_f + (int64_t)band * hf_band;
-      double* __restrict__ ck = ckpt + (int64_t)band * ck_band + lane;
+      double* __restrict__ ck = ckpt + (int64_t)band * ck_band;
       double u[R], pub[S], up_last = 1.0;
 #pragma unroll
       for (int r = 0; r < R; ++r) u[r] = 1.0;
@@ -339,12 +356,12 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
           fetch_up(seg + 1, top, above, pb);
         }
         if (seg > 0) {  // the state before step t0
-          double* __restrict__ cp = ck + (int64_t)(seg - 1) * KS * 64;
+          const uint32_t c0 = (uint32_t)((seg - 1) * KS * 64 + lane);
 #pragma unroll
-          for (int r = 0; r < R; ++r) cp[r * 64] = u[r];
+          for (int r = 0; r < R; ++r) at(ck, c0 + r * 64) = u[r];
 #pragma unroll
-          for (int cc = 0; cc < S; ++cc) cp[(R + cc) * 64] = pub[cc];
-          cp[(R + S) * 64] = up_last;
+          for (int cc = 0; cc < S; ++cc) at(ck, c0 + (R + cc) * 64) = pub[cc];
+          at(ck, c0 + (R + S) * 64) = up_last;
         }
         auto fwd_pass_step = [&](const int j, const FwdIn& in) {
           const int32_t g = t0 + j - lane;
@@ -387,7 +404,7 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
           __syncthreads();
           for (int e = lane; e < C * S; e += 64) {
             const int32_t col = t0 + e / S - 63;
-            if ((uint32_t)col < (uint32_t)total) below[(int64_t)col * S + e % S] = sw[e];
+            if ((uint32_t)col < (uint32_t)total) at(below, (uint32_t)(col * S + e % S)) = sw[e];
           }
         } else if (a.K) {  // the values of the pairs that end in this segment
           __syncthreads();
@@ -410,11 +427,11 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
       const int cb_below = ((row0 + R) >> LAM) - p0;  // coarse row of the cell row below, relative
       float dx[CR][D];
       load_dx(p0, dx);
-      double dxd[CR][D];  // the same increments in double, for the y-side products
+      double dxd[CR][DYA];  // the same increments in double, for the y-side products
 #pragma unroll
       for (int c = 0; c < CR; ++c)
 #pragma unroll
-        for (int k = 0; k < D; ++k) dxd[c][k] = (double)dx[c][k];
+        for (int k = 0; k < DY; ++k) dxd[c][k] = (double)dx[c][k];
       double dxacc[CR][D];
 #pragma unroll
       for (int c = 0; c < CR; ++c)
@@ -423,7 +440,7 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
       const double* __restrict__ above = hand_f + (int64_t)(band > 0 ? band - 1 : 0) * hf_band;
       const double* __restrict__ abl = hand_a + (int64_t)((band + 1) & 1) * ha_buf;
       double* __restrict__ abw = hand_a + (int64_t)(band & 1) * ha_buf;
-      const double* __restrict__ ck = ckpt + (int64_t)band * ck_band + lane;
+      const double* __restrict__ ck = ckpt + (int64_t)band * ck_band;
 
       // lane 63's lower neighbours at steps t0 .. t0 + C - 1 (columns
       // t0 + j - 63; zero outside the task and below the last band)
@@ -436,11 +453,11 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
           const int j = e / LW, f = e - j * LW;
           const int32_t col = t0 + j - 63;
           if (!last && e < NL && (uint32_t)col < (uint32_t)total) {
-            if (f <= S) {
-              pl[i] = abl[(int64_t)col * (S + 1) + f];
+            if (!YS || f <= S) {
+              pl[i] = at(abl, (uint32_t)(col * (S + 1) + f));
             } else {
               const int32_t bq = col / n, qq = col - bq * n;
-              pl[i] = pyt[((int64_t)bq * a.nrows + qq) * D + (f - S - 1)];
+              pl[i] = at(pyt, (uint32_t)((bq * a.nrows + qq) * D + (f - S - 1)));
             }
           }
         }
@@ -454,9 +471,9 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
       };
       auto fetch_ck = [&](int32_t seg, double (&pk)[KS]) {
         if (seg > 0) {
-          const double* __restrict__ cp = ck + (int64_t)(seg - 1) * KS * 64;
+          const uint32_t c0 = (uint32_t)((seg - 1) * KS * 64 + lane);
 #pragma unroll
-          for (int i = 0; i < KS; ++i) pk[i] = cp[i * 64];
+          for (int i = 0; i < KS; ++i) pk[i] = at(ck, c0 + i * 64);
         } else {
 #pragma unroll
           for (int i = 0; i < KS; ++i) pk[i] = 1.0;
@@ -474,9 +491,9 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
       for (int cc = 0; cc < S; ++cc) pubA[cc] = 0.0;
       double prev_ab0 = 0.0;  // lane l+1's top-row a at the next column's first fine column
       float hpub = 0.0f;      // published coefficient (first coarse row)
-      double ypub[D];         // published y-side partial sums
+      double ypub[DYA];       // published y-side partial sums
 #pragma unroll
-      for (int k = 0; k < D; ++k) ypub[k] = 0.0;
+      for (int k = 0; k < DY; ++k) ypub[k] = 0.0;
 
       float4 py[PY];
       double pb[PB], pl[PL], pk[KS];
@@ -544,7 +561,7 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
         // min(g0 + C - 1, total - 1) (none when that is negative)
         const int32_t gl = g0 + C - 1 < total ? g0 + C - 1 : total - 1;
         q = gl > 0 ? gl % n : 0;
-        int64_t cbp = b0 + (gl > 0 ? gl / n : 0);  // pair of the current column
+        int32_t cbp = gl > 0 ? gl / n : 0;  // pair of the current column, from b0
         // reverse step inputs: the lane's y row, lane 63's lower neighbours
         // and, for the steps whose cell sums sit in LDS, those sums
         struct RevIn {
@@ -585,15 +602,15 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
           // the coarse row below the strip is lane l+1's first one (R >= S), or
           // with R < S the lane's own or the next lane's (cb_below)
           const float hb = from_next_lane(hpub, (float)lo[S]);
-          double ych[D];
+          double ych[DYA];
 #pragma unroll
-          for (int k = 0; k < D; ++k) ych[k] = from_next_lane(ypub[k], lo[S + 1 + k]);
+          for (int k = 0; k < DY; ++k) ych[k] = from_next_lane(ypub[k], lo[S + 1 + k]);
           if (real && q == n - 1) {  // last column of a pair: nothing to the right
 #pragma unroll
             for (int r = 0; r < R; ++r) ar[r] = 0.0;
             // the terminal cell (lane 63 of the last band, last row) receives
             // the seed through its below-right neighbour: a = 0 + 0 - (-w)
-            prev_ab0 = (last && lane == 63) ? -pair_weight(a, ia, cbp) : 0.0;
+            prev_ab0 = (last && lane == 63) ? -pair_weight(a, ia, b0 + cbp) : 0.0;
           }
           double gk[CR];
 #pragma unroll
@@ -627,26 +644,26 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
               const int c = (R >= S) ? (r >> LAM) : 0;
               dg[c] = __builtin_fma(v[r][cc], (double)sj[r * S + cc], dg[c]);
             }
-          double ypart[D];
+          double ypart[DYA];
 #pragma unroll
-          for (int k = 0; k < D; ++k) ypart[k] = 0.0;
+          for (int k = 0; k < DY; ++k) ypart[k] = 0.0;
 #pragma unroll
           for (int c = 0; c < CR; ++c) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
               dxacc[c][k] = __builtin_fma(dg[c], (double)dy[k], dxacc[c][k]);
-              ypart[k] = __builtin_fma(dg[c], dxd[c][k], ypart[k]);
+              if (k < DY) ypart[k] = __builtin_fma(dg[c], dxd[c][k], ypart[k]);
             }
           }
 #pragma unroll
-          for (int k = 0; k < D; ++k) ypub[k] = ych[k] + ypart[k];
+          for (int k = 0; k < DY; ++k) ypub[k] = ych[k] + ypart[k];
           // lane 0's outputs: for the band above, and the y-side sums
           if (lane == 0) {
 #pragma unroll
             for (int cc = 0; cc < S; ++cc) sw[j * LW + cc] = v[0][cc];
             sw[j * LW + S] = (double)h32[0];
 #pragma unroll
-            for (int k = 0; k < D; ++k) sw[j * LW + S + 1 + k] = ypub[k];
+            for (int k = 0; k < DY; ++k) sw[j * LW + S + 1 + k] = ypub[k];
           }
           hpub = h32[0];
 #pragma unroll
@@ -710,11 +727,11 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
           const int j = e / LW, f = e - j * LW;
           const int32_t col = t0 + j;
           if ((uint32_t)col < (uint32_t)total) {
-            if (f <= S) {
-              if (!top) abw[(int64_t)col * (S + 1) + f] = sw[e];
+            if (!YS || f <= S) {
+              if (!top) at(abw, (uint32_t)(col * (S + 1) + f)) = sw[e];
             } else {
               const int32_t bq = col / n, qq = col - bq * n;
-              pyt[((int64_t)bq * a.nrows + qq) * D + (f - S - 1)] = sw[e];
+              at(pyt, (uint32_t)((bq * a.nrows + qq) * D + (f - S - 1))) = sw[e];
             }
           }
         }

@@ -85,8 +85,10 @@ int choose_rows_for(int kind, int64_t fine_rows, int lam, int dim);
 
 // Gradient of weighted Gram entries (grad_kernel.h, grad.hip): persistent
 // waves over the tasks of a GradArgs, `slots` of them, each with its own
-// scratch slot (the queue counter is zeroed by a kernel first).
-hipError_t launch_grad(const GradArgs& a, int lam, int dim, int64_t slots, hipStream_t stream);
+// scratch slot (the queue counter is zeroed by a kernel first); ys: form the
+// y-side gradients (a.part_y), else the x side only.
+hipError_t launch_grad(const GradArgs& a, int lam, int dim, bool ys, int64_t slots,
+                       hipStream_t stream);
 bool grad_supported(int lam, int dim);
 
 // Point gradients of one batch from a gradient launch's increment gradients
