@@ -89,6 +89,9 @@ __device__ __forceinline__ T& at(T* base, uint32_t i) {
   return *reinterpret_cast<T*>(reinterpret_cast<C*>(base) + (uint32_t)(i * (uint32_t)sizeof(T)));
 }
 
+// s_waitcnt operand of vmcnt(0) alone (expcnt and lgkmcnt at their maxima)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 // Upstream weight of the solve (x_ia, y_b): in the upper triangle of a
 // symmetric Gram, K[a][b] and K[b][a] are one solve.
 __device__ __forceinline__ double pair_weight(const GradArgs& a, int64_t ia, int64_t b) {
@@ -282,6 +285,16 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
         for (int k = 0; k < D; ++k) dx[c][k] = tr[k];
       }
     };
+    // Steps j (bit j) at which a lane whose column at the segment's first step
+    // is g0 is at the last column of a pair (k n - 1 for some k >= 1) of the
+    // task: the forward values restart there, the adjoint receives its seed.
+    auto pair_end_mask = [&](int32_t g0) -> uint32_t {
+      const int32_t c0 = g0 > 0 ? g0 : 0;
+      const int32_t cend = g0 + C - 1 < total - 1 ? g0 + C - 1 : total - 1;
+      uint32_t mask = 0;
+      for (int32_t e = (c0 / n) * n + n - 1; e <= cend; e += n) mask |= 1u << (e - g0);
+      return mask;
+    };
     // The LDS inputs of a step are read one step ahead (during the previous
     // step's arithmetic), so that their latency is hidden; each step is
     // scheduled on its own (sched_barrier before the read of the next step's
@@ -332,6 +345,10 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
       const int p0 = ((band * 64 + lane) * R - off) >> LAM;  // floor; < 0 for virtual rows
       float dx[CR][D];
       load_dx(p0, dx);
+      // the band's increments have arrived before the segment loop starts:
+      // otherwise the compiler's wait for them can land at the head of a step
+      // loop and cover the staging loads in flight there too (vmcnt(0))
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
       const double* __restrict__ above = hand_f + (int64_t)(band > 0 ? band - 1 : 0) * hf_band;
       double* __restrict__ below = hand_f + (int64_t)band * hf_band;
       double* __restrict__ ck = ckpt + (int64_t)band * ck_band;
@@ -340,7 +357,6 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
       for (int r = 0; r < R; ++r) u[r] = 1.0;
 #pragma unroll
       for (int cc = 0; cc < S; ++cc) pub[cc] = 1.0;
-      int32_t q = 0;
       float4 py[PY];
       double pb[PB];
       fetch_y(0, py);
@@ -355,16 +371,8 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
           fetch_y(seg + 1, py);
           fetch_up(seg + 1, top, above, pb);
         }
-        if (seg > 0) {  // the state before step t0
-          const uint32_t c0 = (uint32_t)((seg - 1) * KS * 64 + lane);
-#pragma unroll
-          for (int r = 0; r < R; ++r) at(ck, c0 + r * 64) = u[r];
-#pragma unroll
-          for (int cc = 0; cc < S; ++cc) at(ck, c0 + (R + cc) * 64) = pub[cc];
-          at(ck, c0 + (R + S) * 64) = up_last;
-        }
+        const uint32_t pe = pair_end_mask(t0 - lane);
         auto fwd_pass_step = [&](const int j, const FwdIn& in) {
-          const int32_t g = t0 + j - lane;
           float st[1];
           forward_step(in, dx, u, pub, up_last, st);
           // lane 63's bottom row: for the band below, or in the last band the
@@ -373,12 +381,11 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
 #pragma unroll
             for (int cc = 0; cc < S; ++cc) sw[j * S + cc] = pub[cc];
           }
-          if ((uint32_t)g < (uint32_t)total && ++q == n) {
+          if ((pe >> j) & 1u) {
             // last column of a pair: the left boundary of the next pair
 #pragma unroll
             for (int r = 0; r < R; ++r) u[r] = 1.0;
             up_last = 1.0;
-            q = 0;
           }
         };
         // two steps per iteration, alternating two input buffers (the read
@@ -413,6 +420,18 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
             if ((uint32_t)col < (uint32_t)total && (col + 1) % n == 0)
               store_value(a, ia, b0 + col / n, (float)sw[j * S + S - 1]);
           }
+        }
+        // the checkpoint of the next segment: the state before its first step.
+        // (Stored at the end of the segment, before the next staging loads:
+        // the next step loop overwrites these registers, and a wait for the
+        // stores then leaves the later loads in flight.)
+        if (seg + 1 < nseg) {
+          const uint32_t c0 = (uint32_t)(seg * KS * 64 + lane);
+#pragma unroll
+          for (int r = 0; r < R; ++r) at(ck, c0 + r * 64) = u[r];
+#pragma unroll
+          for (int cc = 0; cc < S; ++cc) at(ck, c0 + (R + cc) * 64) = pub[cc];
+          at(ck, c0 + (R + S) * 64) = up_last;
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -516,15 +535,13 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
 #pragma unroll
         for (int cc = 0; cc < S; ++cc) pub[cc] = pk[R + cc];
         up_last = pk[R + S];
-        int32_t q = g0 > 0 ? g0 % n : 0;
+        const uint32_t pe = pair_end_mask(g0);
         auto recompute_step = [&](const int j, const FwdIn& in, float (&st)[RS]) {
-          const int32_t g = g0 + j;
           forward_step(in, dx, u, pub, up_last, st);
-          if ((uint32_t)g < (uint32_t)total && ++q == n) {
+          if ((pe >> j) & 1u) {
 #pragma unroll
             for (int r = 0; r < R; ++r) u[r] = 1.0;
             up_last = 1.0;
-            q = 0;
           }
         };
         auto put_sums = [&](const int j, const float (&st)[RS]) {
@@ -557,11 +574,7 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
           recompute_step(j, fi[(j - CL) & 1], sv[j - CL]);
         }
 
-        // the segment's reverse steps; a lane's first real one is at column
-        // min(g0 + C - 1, total - 1) (none when that is negative)
-        const int32_t gl = g0 + C - 1 < total ? g0 + C - 1 : total - 1;
-        q = gl > 0 ? gl % n : 0;
-        int32_t cbp = gl > 0 ? gl / n : 0;  // pair of the current column, from b0
+        // the segment's reverse steps
         // reverse step inputs: the lane's y row, lane 63's lower neighbours
         // and, for the steps whose cell sums sit in LDS, those sums
         struct RevIn {
@@ -584,8 +597,6 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
           }
         };
         auto rev_step = [&](const int j, const RevIn& in, const float(&sj)[RS]) {
-          const int32_t g = g0 + j;
-          const bool real = (uint32_t)g < (uint32_t)total;
           const float(&dy)[DP] = in.dy;
           const double(&lo)[LW] = in.lo;
           float h32[CR];
@@ -605,12 +616,12 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
           double ych[DYA];
 #pragma unroll
           for (int k = 0; k < DY; ++k) ych[k] = from_next_lane(ypub[k], lo[S + 1 + k]);
-          if (real && q == n - 1) {  // last column of a pair: nothing to the right
+          if ((pe >> j) & 1u) {  // last column of a pair: nothing to the right
 #pragma unroll
             for (int r = 0; r < R; ++r) ar[r] = 0.0;
             // the terminal cell (lane 63 of the last band, last row) receives
             // the seed through its below-right neighbour: a = 0 + 0 - (-w)
-            prev_ab0 = (last && lane == 63) ? -pair_weight(a, ia, b0 + cbp) : 0.0;
+            prev_ab0 = (last && lane == 63) ? -pair_weight(a, ia, b0 + (g0 + j) / n) : 0.0;
           }
           double gk[CR];
 #pragma unroll
@@ -673,10 +684,6 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
           for (int r = 0; r < R; ++r) ar[r] = v[r][0];
 #pragma unroll
           for (int c = 0; c < CR; ++c) gr[c] = gk[c];
-          if (real && --q < 0) {  // first column of the pair done: the pair on the left
-            q = n - 1;
-            --cbp;
-          }
         };
         // inputs read one step ahead, alternating two buffers
         RevIn ri[2];
