@@ -87,14 +87,14 @@ def grad_ops_per_cell(d: int, lam: int) -> float:
 
 
 # checkpoint traffic of the gradient kernel per fine cell (written once, read
-# once): R + 2^lam + 1 doubles per lane every C steps of R 2^lam cells, with R
-# = 4 rows per lane and C the segment length (see grad_args.h)
+# once): R + 2^lam doubles per lane every C steps of R 2^lam cells, with R = 4
+# rows per lane and C the segment length (see grad_args.h)
 def grad_checkpoint_bytes_per_cell(d: int, lam: int) -> float:
     R = 4
     S = 1 << lam
-    floats_reg = (32 if d > 8 else 64) // (2 if lam == 0 else 1)
+    floats_reg = 32 // (2 if lam == 0 else 1)
     C = max(1, floats_reg // (R * S)) + max(1, 64 // (R * S))
-    return 2.0 * 8.0 * (R + S + 1) / (R * S * C)
+    return 2.0 * 8.0 * (R + S) / (R * S * C)
 
 
 # the files the Gram sweep kernel compiles from (its translation unit and headers)

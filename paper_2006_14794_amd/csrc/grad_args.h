@@ -61,11 +61,13 @@ __host__ __device__ constexpr int grad_segment(int lam, int d) {
   return grad_reg_steps(lam, d) + grad_lds_steps(lam);
 }
 
-// Doubles of the wave state saved per lane at a checkpoint: the lane's R
-// values at its last fine column, its bottom row at the 2^lam fine columns
-// of its last step, and the upper-left neighbour of its next block.
+// Doubles of the wave state saved per lane at a checkpoint: the lane's first
+// R - 1 values at its last fine column, its bottom row at the 2^lam fine
+// columns of its last step (whose last entry is the R-th value, unless that
+// column ended a pair and the values restarted at 1), and the upper-left
+// neighbour of its next block.
 __host__ __device__ constexpr int grad_state_doubles(int lam) {
-  return kGradRows + (1 << lam) + 1;
+  return kGradRows + (1 << lam);
 }
 
 // Scratch of one wave slot, in doubles:

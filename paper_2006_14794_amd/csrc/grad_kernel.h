@@ -23,7 +23,7 @@
 //  * Forward pass, bands top to bottom: the forward sweep's wavefront (one
 //    coarse column per step, lane l lagging lane l-1 by one step, DPP
 //    wave_shr:1 between lanes).  A band's bottom row goes to `hand_f` for the
-//    band below; every C steps each lane saves its state (R + 2^lambda + 1
+//    band below; every C steps each lane saves its state (R + 2^lambda
 //    doubles) as a checkpoint; the last band writes the terminal values.
 //  * Adjoint pass, bands bottom to top.  Lane l handles coarse column t - l
 //    at forward step t, and the reverse wavefront (lane 63 leading) reaches
@@ -44,7 +44,7 @@
 //  * Inputs of a segment (y rows, the neighbouring bands' rows) are staged
 //    in LDS one segment ahead; outputs for the neighbouring bands are staged
 //    in LDS and written out once per segment.
-// HBM traffic per fine cell: the checkpoints, 8 (R + 2^lambda + 1) /
+// HBM traffic per fine cell: the checkpoints, 8 (R + 2^lambda) /
 // (R 2^lambda C) bytes written once and read once, instead of a stored cell
 // sum per fine cell.
 #pragma once
@@ -129,7 +129,7 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
   constexpr int S = 1 << LAM;
   constexpr int CR = (R >> LAM) > 0 ? (R >> LAM) : 1;
   constexpr int RS = R * S;
-  constexpr int KS = R + S + 1;
+  constexpr int KS = R + S;               // checkpoint doubles per lane
   constexpr int C = CL + CG;
   constexpr int G4 = RS / 4;              // float4 groups of one lane's cell sums per step
   constexpr int Y4 = (C + 63) * DP / 4;   // float4s of a segment's y rows
@@ -428,10 +428,10 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
         if (seg + 1 < nseg) {
           const uint32_t c0 = (uint32_t)(seg * KS * 64 + lane);
 #pragma unroll
-          for (int r = 0; r < R; ++r) at(ck, c0 + r * 64) = u[r];
+          for (int r = 0; r < R - 1; ++r) at(ck, c0 + r * 64) = u[r];
 #pragma unroll
-          for (int cc = 0; cc < S; ++cc) at(ck, c0 + (R + cc) * 64) = pub[cc];
-          at(ck, c0 + (R + S) * 64) = up_last;
+          for (int cc = 0; cc < S; ++cc) at(ck, c0 + (R - 1 + cc) * 64) = pub[cc];
+          at(ck, c0 + (R - 1 + S) * 64) = up_last;
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -531,10 +531,14 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 && LAM < 3 ? 2 : 1, 2))) void grad_ker
         // recompute the segment's forward steps from its checkpoint
         double u[R], pub[S], up_last;
 #pragma unroll
-        for (int r = 0; r < R; ++r) u[r] = pk[r];
+        for (int r = 0; r < R - 1; ++r) u[r] = pk[r];
 #pragma unroll
-        for (int cc = 0; cc < S; ++cc) pub[cc] = pk[R + cc];
-        up_last = pk[R + S];
+        for (int cc = 0; cc < S; ++cc) pub[cc] = pk[R - 1 + cc];
+        up_last = pk[R - 1 + S];
+        {  // the last value: the bottom row's last entry, or 1 after a pair's end
+          const int32_t cl = g0 - 1;
+          u[R - 1] = ((uint32_t)cl < (uint32_t)total && (cl + 1) % n == 0) ? 1.0 : pub[S - 1];
+        }
         const uint32_t pe = pair_end_mask(g0);
         auto recompute_step = [&](const int j, const FwdIn& in, float (&st)[RS]) {
           forward_step(in, dx, u, pub, up_last, st);
