@@ -494,7 +494,7 @@ sk_status sigkernel_channel_stats(const void *x, int32_t x_dtype, const float *s
  * per pair on chip (one workgroup per pair, activations in LDS; the same
  * arithmetic as sigkernel_corrector_forward, bit for bit), then
  *   k_hat = k0 + mu + sigma y0,  e = sigma exp(y1);
- * a pair falls back when kappa e > tol max(1, |k_hat|) and then receives the
+ * a pair falls back unless kappa e <= tol |k_hat| and then receives the
  * plain scheme at `fallback_order` (out), computed on the device for exactly
  * those pairs (no host synchronisation).  out: float[n]; err (nullable):
  * float[n] predicted errors; fallback (nullable): int32[n], 1 where the plain

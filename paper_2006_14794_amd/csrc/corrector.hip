@@ -701,7 +701,8 @@ __global__ __launch_bounds__(256) void decide_kernel(const DecideArgs a) {
     const float y0 = a.y[2 * i], y1 = a.y[2 * i + 1];
     const float k = a.k0[i] + mu + sigma * y0;
     const float err = sigma * expf(y1);
-    fb = a.kappa * err > a.tol * fmaxf(1.0f, fabsf(k));
+    // relative: kappa e <= tol |k_hat| accepts (NaN falls back)
+    fb = !(a.kappa * err <= a.tol * fabsf(k));
     a.out[i] = k;
     if (a.err) a.err[i] = err;
     if (a.fallback) a.fallback[i] = fb ? 1 : 0;

@@ -91,7 +91,7 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eval-pairs", type=int, default=65536)
-    ap.add_argument("--kappa", type=float, default=3.0)
+    ap.add_argument("--kappa", type=float, default=corr.KAPPA)
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--out", default=None, help="weights file (.npz)")
     ap.add_argument("--summary", default=None, help="JSON summary file")

@@ -266,11 +266,12 @@ def test_predict_fallback_is_the_plain_order3_solve():
     assert int(fb_inf.sum().item()) == 0
     # a threshold in between: every pair is either its corrected value or the
     # plain solve, exactly as the predicted error decides
-    tol = float(np.median(3.0 * e_inf.cpu().numpy() / np.maximum(1, np.abs(k_inf.cpu().numpy()))))
-    out, err, fb = c.predict(Xc, Yc, tol=tol)
+    tol = float(np.median(3.0 * e_inf.cpu().numpy() / np.abs(k_inf.cpu().numpy())))
+    out, err, fb = c.predict(Xc, Yc, kappa=3.0, tol=tol)
     fbn = fb.cpu().numpy().astype(bool)
     assert 0 < fbn.sum() < n
-    expect = 3.0 * err.cpu().numpy() > tol * np.maximum(1.0, np.abs(k_inf.cpu().numpy()))
+    # accepted where kappa e <= tol |k_hat| (float32 products, as on the device)
+    expect = ~(np.float32(3.0) * err.cpu().numpy() <= np.float32(tol) * np.abs(k_inf.cpu().numpy()))
     assert np.array_equal(fbn, expect)
     o = out.cpu().numpy()
     assert np.array_equal(o[fbn], plain.cpu().numpy()[fbn])

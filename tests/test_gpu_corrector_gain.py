@@ -47,17 +47,36 @@ def test_trained_corrector_beats_order0(held_out):
 
 
 def test_fallback_keeps_the_error_bound(held_out):
+    # the default margin (corr.KAPPA, chosen on calibration pairs of another
+    # seed) holds every pair of the held-out set within 1e-3 of order 3
     Xc, Yc, k3 = held_out
     model = sk.Corrector.load(WEIGHTS)
-    out, err, fb = model.predict(Xc, Yc, kappa=3.0, tol=1e-3)
+    out, err, fb = model.predict(Xc, Yc, tol=1e-3)
     e = rel(out.cpu().numpy(), k3)
     fbn = fb.cpu().numpy().astype(bool)
-    print(f"fallback {fbn.mean():.4f}; median {np.median(e):.3e} p99 {np.percentile(e, 99):.3e} "
-          f"max {e.max():.3e}")
-    assert fbn.mean() < 0.05
+    print(f"kappa {corr.KAPPA}: fallback {fbn.mean():.4f}; median {np.median(e):.3e} "
+          f"p99 {np.percentile(e, 99):.3e} max {e.max():.3e}")
+    assert fbn.mean() < 0.2
     assert np.all(e[fbn] <= 1e-6)  # the plain order-3 solve itself
-    assert np.percentile(e, 99) <= 1e-3
+    assert e.max() <= 1e-3
     # predicted errors are informative: the accepted pairs' errors are mostly
     # within three predicted standard deviations
     pe = err.cpu().numpy()[~fbn] / np.abs(out.cpu().numpy()[~fbn])
     assert np.mean(e[~fbn] <= 3 * pe) > 0.95
+
+
+def test_extrapolation_baseline(held_out):
+    # the non-learned alternative from the same scheme: orders 0 and 1
+    # extrapolated to order 3 under an error c 4^-lambda.  Printed beside the
+    # corrector; on this workload it is the more accurate of the two.
+    Xc, Yc, k3 = held_out
+    k0 = sk.sigkernel_pair(Xc, Yc, 0).cpu().numpy().astype(np.float64)
+    k1 = sk.sigkernel_pair(Xc, Yc, 1).cpu().numpy().astype(np.float64)
+    ext = k0 + (63.0 / 64.0) * (4.0 / 3.0) * (k1 - k0)
+    model = sk.Corrector.load(WEIGHTS)
+    raw, _, _ = model.predict(Xc, Yc, tol=1e30)
+    ex, ec = rel(ext, k3), rel(raw.cpu().numpy(), k3)
+    print(f"extrapolation(0, 1): median {np.median(ex):.3e} max {ex.max():.3e}; "
+          f"corrector: median {np.median(ec):.3e} max {ec.max():.3e}")
+    # the extrapolation is the order-3 value to the scheme's own accuracy here
+    assert np.median(ex) < 5e-5 and ex.max() < 2e-3
