@@ -53,9 +53,10 @@ def parse():
     ap.add_argument("--cpu-sample-pairs", type=int, default=0,
                     help="pairs of the workload timed on the CPU oracle (0: all)")
     ap.add_argument("--workload", choices=["gram", "mmd", "ragged", "increment_gram", "corrector",
-                                           "lifted", "fig3", "reduce"],
+                                           "lifted", "fig3", "reduce", "pair"],
                     default="gram",
                     help="gram: the 128 x 128 Gram batch (default, the reported metric); "
+                         "pair: one 32-point pair in R^2 at order 0 (latency per call); "
                          "mmd: unbiased MMD^2 of 64 vs 64 512-point paths with its gradient; "
                          "ragged: 4096 independent pairs of uneven lengths; "
                          "increment_gram: the coarse Gram of the Gram batch on the matrix cores; "
@@ -286,7 +287,7 @@ def bench_mmd(args):
     }
     if not args.no_cpu_baseline:
         import oracle
-        ns = 16  # the first 16 generated and 16 target paths: the same estimator and gradient
+        ns = X.shape[0]  # the whole workload: all 64 generated and 64 target paths
         Xs, Ys = X[:ns].astype(np.float64), Y[:ns].astype(np.float64)
         threads = oracle.max_threads()
         t0 = time.perf_counter()
@@ -303,9 +304,9 @@ def bench_mmd(args):
         s_cells = (3 * ns * ns + 2 * ns * ns) * cells
         rec["cpu_baseline"] = {
             "value": s_cells / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"MMD^2 value and gradient of the first {ns} vs {ns} paths (full Gram "
-                      f"blocks and full backward blocks, {s_cells:.3g} cells), all host threads, "
-                      f"{dt:.2f} s", **host_cpu()}
+            "sample": f"the whole workload: MMD^2 value and gradient of all {ns} vs {ns} paths "
+                      f"(full Gram blocks and full backward blocks, {s_cells:.3g} cells), all "
+                      f"host threads, {dt:.2f} s", **host_cpu()}
     emit(rec)
 
 
@@ -728,6 +729,60 @@ def bench_corrector(args):
     emit(rec)
 
 
+def bench_pair(args):
+    """One pair of 32-point paths in R^2 (N(0, 1/32) increments), dyadic order
+    0: the latency of a single sigkernel_pair call, eager and as a hipGraph
+    replay, with the straight-segment pair against the closed form."""
+    import torch
+    import paper_2006_14794_amd as sk
+    import workloads
+    import oracle
+    x, y, xs, ys = workloads.single_pair()
+    dev = torch.device("cuda:0")
+    xt, yt = torch.from_numpy(x[None]).to(dev), torch.from_numpy(y[None]).to(dev)
+    out = torch.empty(1, dtype=torch.float32, device=dev)
+    ws = torch.empty(sk.workspace_bytes(0, xt, yt, 0, 0), dtype=torch.uint8, device=dev)
+
+    def call():
+        sk.sigkernel_pair(xt, yt, 0, out=out, workspace=ws)
+    graph, gout = sk.capture_pair(xt, yt, 0)
+    per_e, wall_e = time_steps(call, args.steps, args.warmup)
+    per_g, wall_g = time_steps(graph.replay, args.steps, args.warmup)
+    us_e = wall_e * 1e6 / args.steps
+    us_g = wall_g * 1e6 / args.steps
+    ref = float(oracle.pairs([x.astype(np.float64)], [y.astype(np.float64)], 0)[0])
+    k = float(gout.item())
+    # the straight segments: the scheme converges to k = sum_k <a,b>^k / (k!)^2
+    # under dyadic refinement (order 0 is a single cell, 1 + <a,b>)
+    xsd, ysd = torch.from_numpy(xs[None]).to(dev), torch.from_numpy(ys[None]).to(dev)
+    c = float(np.dot((xs[1] - xs[0]).astype(np.float64), (ys[1] - ys[0]).astype(np.float64)))
+    closed = oracle.straight_segment_kernel(c)
+    seg = {f"order_{o}": sk.sigkernel_pair(xsd, ysd, o).item() for o in (0, 2, 4, 6, 8)}
+    rec = {
+        "metric": "pairs/s of single-pair calls (latency), 32-point pair in R^2, order 0",
+        "value": 1e6 / us_g, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": us_g / 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "one pair, 32 points in R^2, N(0, 1/32) increments from 0, "
+                               "dyadic order 0; and one straight-segment pair"},
+        "us_per_pair": {"hipgraph_replay": us_g, "eager_call": us_e,
+                        "gpu_event_per_launch": per_g[0] * 1e3},
+        "rel_err_vs_oracle": abs(k - ref) / abs(ref),
+        "straight_segment": {"inner_product": c, "closed_form": closed, "gpu": seg,
+                             "rel_err": {k: abs(v - closed) / abs(closed) for k, v in seg.items()}},
+    }
+    if not args.no_cpu_baseline:
+        xd, yd = [x.astype(np.float64)] * 100000, [y.astype(np.float64)] * 100000
+        t0 = time.perf_counter()
+        oracle.pairs(xd, yd, 0, nthreads=1)
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": len(xd) / dt, "unit": "pairs/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"the same pair solved {len(xd)} times on one host thread, "
+                                         f"{dt:.2f} s", **host_cpu()}
+    emit(rec)
+
+
 def copy_calibration(args):
     """A plain device-to-device copy of 1 GiB, repeated: the reference
     dispatch for the HBM byte counters."""
@@ -771,6 +826,9 @@ def main():
         return
     if args.workload == "reduce":
         bench_reduce(args)
+        return
+    if args.workload == "pair":
+        bench_pair(args)
         return
 
     import torch
