@@ -198,23 +198,23 @@ def test_ragged_broken_path_gives_nan_gradient_for_its_pairs():
     assert np.all(np.isnan(gy.cpu().numpy()))  # every y path meets the broken one
 
 
-@pytest.mark.parametrize("lam", [0, 1, 3])
+@pytest.mark.parametrize("lam,d", [(0, 4), (1, 4), (3, 4), (2, 16), (0, 9), (3, 1)])
 @pytest.mark.parametrize("lx", [40, 300])
-def test_x_only_and_y_only_gradients(lam, lx):
+def test_x_only_and_y_only_gradients(lam, d, lx):
     # dY not asked for: the kernel skips the y-side sums (a kernel of its own);
     # dX not asked for: the y side alone.  Both against the full oracle adjoint,
     # with an x path of one band and one of several.
-    X = workloads.random_paths(1010 + lx, 3, lx, 4, std=0.3 / np.sqrt(lx))
-    Y = workloads.random_paths(1011 + lx, 4, 29, 4, std=0.3 / 5)
+    X = workloads.random_paths(1010 + lx, 3, lx, d, std=0.3 / np.sqrt(lx))
+    Y = workloads.random_paths(1011 + lx, 4, 29, d, std=0.3 / 5)
     dK = np.random.default_rng(lam + lx).normal(size=(3, 4)).astype(np.float32)
     rx, ry = oracle.gram_backward(X.astype(np.float64), Y.astype(np.float64),
                                   dK.astype(np.float64), lam)
     gx, gy = sk.sigkernel_gram_backward(cuda(X), cuda(Y), cuda(dK), lam, need_y=False)
     assert gy is None
-    close(gx.cpu().numpy(), rx, f"dX x-only L{lx} lam{lam}")
+    close(gx.cpu().numpy(), rx, f"dX x-only L{lx} lam{lam} d{d}")
     gx2, gy2 = sk.sigkernel_gram_backward(cuda(X), cuda(Y), cuda(dK), lam, need_x=False)
     assert gx2 is None
-    close(gy2.cpu().numpy(), ry, f"dY y-only L{lx} lam{lam}")
+    close(gy2.cpu().numpy(), ry, f"dY y-only L{lx} lam{lam} d{d}")
     # the x-only kernel gives the same dX as the kernel with the y side
     gx3, _ = sk.sigkernel_gram_backward(cuda(X), cuda(Y), cuda(dK), lam)
     assert torch.equal(gx, gx3)
