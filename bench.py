@@ -725,6 +725,8 @@ def bench_corrector(args):
                       f"{dt:.2f} s; the metric's per-pair work at order 3, so the rate compares "
                       "with value directly",
             "gpu_plain_max_err_on_sample": float(np.max(np.abs(k3[idx] - ref) / np.abs(ref))),
+            "extrapolated_whole_workload_s": dt * n / len(idx),
+            "extrapolation": "by fine-cell count (every pair has the same cells)",
             **host_cpu()}
     emit(rec)
 
