@@ -193,7 +193,12 @@ sk_status sigkernel_gram_backward(const sk_paths *X, const sk_paths *Y, int32_t 
  * written to HBM for every pair: gram = 1 enumerates (a, b) as a * Y->n_paths
  * + b, gram = 0 the pairs (x_k, y_k) (equal batch sizes).
  *  - Uniform batches of at most 16 channels; G0: DEVICE
- *    float[pairs][X->len - 1][Y->len - 1].
+ *    float[pairs][X->len - 1][ldg], of which columns q < Y->len - 1 are
+ *    written (the rest of each row is left as it was).  ldg = 0 means the
+ *    dense layout, ldg = Y->len - 1; a nonzero ldg below that gives
+ *    SK_ERR_SHAPE (nothing is enqueued).  A padded stride lets the caller
+ *    align rows (a multiple of 32 floats with a 128-byte aligned G0 puts
+ *    every row on cache-line boundaries).
  *  - flags: SK_GRAM_BF16 / SK_GRAM_F16 round the increments to 16 bits (the
  *    products and sums stay float32); otherwise float32 throughout.
  *  - No workspace.  Paths with one point give an empty G0 (nothing written).
@@ -203,7 +208,7 @@ sk_status sigkernel_gram_backward(const sk_paths *X, const sk_paths *Y, int32_t 
  * callers that need the coarse Gram itself.
  */
 sk_status sigkernel_increment_gram(const sk_paths *X, const sk_paths *Y, int32_t gram,
-                                   uint32_t flags, float *G0, void *stream);
+                                   uint32_t flags, float *G0, int64_t ldg, void *stream);
 
 /*
  * sigkernel_mmd2 -- unbiased MMD^2 between the laws of two batches of paths

@@ -147,6 +147,7 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER(SkPaths)
     vp, i32, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
+    i64 = ctypes.c_int64
     lib.sigkernel_pair.argtypes = [P, P, i32, u32, vp, vp, sz, vp]
     lib.sigkernel_pair.restype = i32
     lib.sigkernel_gram.argtypes = [P, P, i32, u32, vp, vp, sz, vp]
@@ -169,7 +170,7 @@ def load():
     lib.sigkernel_gram_backward.restype = i32
     lib.sigkernel_mmd2.argtypes = [P, P, i32, u32, vp, vp, vp, sz, vp]
     lib.sigkernel_mmd2.restype = i32
-    lib.sigkernel_increment_gram.argtypes = [P, P, i32, u32, vp, vp]
+    lib.sigkernel_increment_gram.argtypes = [P, P, i32, u32, vp, i64, vp]
     lib.sigkernel_increment_gram.restype = i32
     lib.sigkernel_workspace_bytes.argtypes = [i32, P, P, i32, u32]
     lib.sigkernel_workspace_bytes.restype = sz

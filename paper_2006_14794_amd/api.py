@@ -421,19 +421,24 @@ def mmd2(X: torch.Tensor, Y: torch.Tensor, dyadic_order: int = 0) -> torch.Tenso
 
 
 def sigkernel_increment_gram(X: torch.Tensor, Y: torch.Tensor, *, gram: bool = True,
-                             precision: str = "f32",
+                             precision: str = "f32", ld: Optional[int] = None,
                              out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """G0 = <x_{p+1} - x_p, y_{q+1} - y_q> of every pair on the matrix cores:
-    [nx, ny, Lx-1, Ly-1] (gram) or [n, Lx-1, Ly-1] (pairs)."""
+    [nx, ny, Lx-1, Ly-1] (gram) or [n, Lx-1, Ly-1] (pairs).  ``ld`` (>= Ly-1)
+    stores each row with that stride: ``out`` then has ld columns, of which
+    the first Ly-1 are written and returned as a view."""
     lib = _lib.load()
     sx, sy = _describe(X), _describe(Y)
     m, n = int(X.shape[1]) - 1, int(Y.shape[1]) - 1
-    shape = (int(X.shape[0]), int(Y.shape[0]), m, n) if gram else (int(X.shape[0]), m, n)
+    cols = n if ld is None else int(ld)
+    lead = (int(X.shape[0]), int(Y.shape[0])) if gram else (int(X.shape[0]),)
     if out is None:
-        out = torch.empty(shape, dtype=torch.float32, device=X.device)
+        out = torch.empty(lead + (m, cols), dtype=torch.float32, device=X.device)
+    elif tuple(out.shape) != lead + (m, cols) or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous float32 tensor of shape {lead + (m, cols)}")
     st = lib.sigkernel_increment_gram(ctypes.byref(sx), ctypes.byref(sy), 1 if gram else 0,
                                       _gram_flag(precision),
                                       out.data_ptr() if out.numel() else None,
-                                      _stream_ptr(X.device))
+                                      0 if ld is None else cols, _stream_ptr(X.device))
     _lib.check(st, "sigkernel_increment_gram")
-    return out
+    return out if ld is None else out[..., :n]

@@ -1120,13 +1120,14 @@ sk_status sigkernel_reduced_measure_support(const float* K, const float* alpha, 
 }
 
 sk_status sigkernel_increment_gram(const sk_paths* X, const sk_paths* Y, int32_t gram,
-                                  uint32_t flags, float* G0, void* stream) {
+                                  uint32_t flags, float* G0, int64_t ldg, void* stream) {
   if (!X || !Y) return SK_ERR_NULL;
   if (!valid_batch(X) || !valid_batch(Y) || X->dim != Y->dim) return SK_ERR_SHAPE;
   if (gram != 0 && gram != 1) return SK_ERR_FLAGS;
   if (!gram && X->n_paths != Y->n_paths) return SK_ERR_SHAPE;
   if (sk_status f = check_flags(flags, SK_GRAM_BF16 | SK_GRAM_F16)) return f;
   if (X->offsets || Y->offsets) return SK_ERR_UNSUPPORTED;
+  if (ldg != 0 && ldg < (int64_t)Y->len - 1) return SK_ERR_SHAPE;
   const int64_t pairs = gram ? X->n_paths * Y->n_paths : X->n_paths;
   if (pairs == 0 || X->len < 2 || Y->len < 2) return SK_OK;
   if (!G0 || !X->points || !Y->points) return SK_ERR_NULL;
@@ -1141,6 +1142,7 @@ sk_status sigkernel_increment_gram(const sk_paths* X, const sk_paths* Y, int32_t
   a.ny = Y->n_paths;
   a.gram = gram;
   a.g0 = G0;
+  a.ld = ldg ? ldg : (int64_t)Y->len - 1;
   const hipError_t e =
       sk::launch_gram_mfma(a, rounding_of(flags), static_cast<hipStream_t>(stream));
   if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;

@@ -14,9 +14,12 @@
 // Operands are the increments themselves, formed from the staged points.  Lane l supplies row (l mod 32) of the x tile and column (l mod 32)
 // of the y tile; its half (l / 32) selects the channel slice.  Accumulator
 // register r of lane l holds row 8 (r / 4) + 4 (l / 32) + (r mod 4), column
-// l mod 32, and is stored from there (through LDS and 16-byte stores it
-// took 1.57 ms for the 128 x 128 Gram of 256-point paths, 1.35 ms directly;
-// with a 4-byte copy loop 1.88 ms).
+// l mod 32, and is stored from there: each store instruction writes 32
+// consecutive floats of two rows.  The kernel is bound by these stores; on
+// the 128 x 128 Gram of 256-point paths the forms measured are listed with
+// the design notes (whole-line 16-byte stores from a wave-private LDS
+// transpose, and whole rows written in order from a workgroup-wide block in
+// LDS, were not faster).
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -46,7 +49,8 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(const GramArgs a) {
   const int32_t rows = m - p0 < 32 ? m - p0 : 32;
   const float* __restrict__ xp = a.x + (ia * (int64_t)a.x_len + p0) * d;
   const float* __restrict__ yq = a.y + ib * (int64_t)a.y_len * d;
-  float* __restrict__ g = a.g0 + pair * (int64_t)m * n + (int64_t)p0 * n;
+  const int64_t ld = a.ld;  // row stride of G0, >= n
+  float* __restrict__ g = a.g0 + pair * (int64_t)m * ld + (int64_t)p0 * ld;
   for (int e = threadIdx.x; e < (rows + 1) * d; e += blockDim.x) xs[e] = xp[e];
   const int32_t row = lane & 31, half = lane >> 5;
   auto xinc = [&](int k) -> float {
@@ -95,7 +99,7 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(const GramArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int32_t R = 8 * (r >> 2) + 4 * half + (r & 3);
-        if (R < rows && c < cw) g[(int64_t)R * n + c0 + c] = acc[r];
+        if (R < rows && c < cw) g[(int64_t)R * ld + c0 + c] = acc[r];
       }
     }
   }
@@ -107,6 +111,7 @@ hipError_t launch_gram_mfma(const GramArgs& a, int precision, hipStream_t stream
   const int32_t m = a.x_len - 1, n = a.y_len - 1;
   const int64_t pairs = a.gram ? a.nx * a.ny : a.nx;
   if (m <= 0 || n <= 0 || pairs == 0) return hipSuccess;
+  if (a.ld < n) return hipErrorInvalidValue;
   const int64_t row_blocks = (m + 31) / 32;
   if (row_blocks > 65535 || pairs > 0x7FFFFFFF) return hipErrorInvalidValue;
   const dim3 grid((unsigned)pairs, (unsigned)row_blocks, 1);

@@ -242,7 +242,8 @@ struct GramArgs {
   int32_t x_len, y_len, d;
   int64_t nx, ny;
   int32_t gram;             // 1: every (a, b), pair index a ny + b; 0: pairs (x_k, y_k)
-  float* g0;                // [pairs][x_len - 1][y_len - 1]
+  float* g0;                // [pairs][x_len - 1][ld], columns < y_len - 1 written
+  int64_t ld;               // row stride of g0 in floats, >= y_len - 1
 };
 // precision: kRoundNone (float32 MFMA), kRoundBf16, kRoundF16
 hipError_t launch_gram_mfma(const GramArgs& a, int precision, hipStream_t stream);

@@ -181,9 +181,17 @@ def test_implicit_flag_only_where_defined():
     assert lib.sigkernel_gram_backward(ctypes.byref(X), ctypes.byref(X), 1, _lib.SK_IMPLICIT,
                                        FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == _lib.SK_ERR_FLAGS
     assert lib.sigkernel_increment_gram(ctypes.byref(X), ctypes.byref(X), 1, _lib.SK_IMPLICIT,
-                                        FAKE, None) == _lib.SK_ERR_FLAGS
+                                        FAKE, 0, None) == _lib.SK_ERR_FLAGS
     assert lib.sigkernel_mmd2(ctypes.byref(X), ctypes.byref(X), 1, _lib.SK_IMPLICIT, FAKE, FAKE,
                               FAKE, 1 << 30, None) == _lib.SK_ERR_FLAGS
+
+
+def test_increment_gram_row_stride_below_the_row_length_is_a_shape_error():
+    lib = _lib.load()
+    X, Y = paths(L=16), paths(L=40)
+    for ldg in (1, 38):  # rows of Y->len - 1 = 39 floats
+        assert lib.sigkernel_increment_gram(ctypes.byref(X), ctypes.byref(Y), 1, 0, FAKE, ldg,
+                                            None) == _lib.SK_ERR_SHAPE
 
 
 def call_lifted(fn, X, Y, kernel, lam=1, flags=0, out=FAKE, ws=FAKE, nbytes=1 << 30):

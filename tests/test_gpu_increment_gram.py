@@ -47,6 +47,47 @@ def test_gram_tiles_and_channels(precision, d, lx, ly):
     assert np.abs(G - ref).max() <= 2e-6 * scale
 
 
+@pytest.mark.parametrize("ld", [None, 256, 259, 260])
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_row_stride_layouts(precision, ld):
+    # dense rows (255 floats), rows padded to 256 floats, a stride that is
+    # not a multiple of four floats and another padded multiple of four; the
+    # padding columns are left untouched
+    X = workloads.random_paths(400, 3, 256, 9)
+    Y = workloads.random_paths(401, 2, 256, 9)
+    Xc, Yc = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    out = None
+    if ld is not None:
+        out = torch.full((3, 2, 255, ld), -7.0, dtype=torch.float32, device="cuda")
+    G = sk.sigkernel_increment_gram(Xc, Yc, precision=precision, ld=ld, out=out).cpu().numpy()
+    ix, iy = rounded_increments(X, precision), rounded_increments(Y, precision)
+    ref = np.einsum("apc,bqc->abpq", ix, iy)
+    scale = np.einsum("apc,bqc->abpq", np.abs(ix), np.abs(iy)).max()
+    assert G.shape == ref.shape
+    assert np.abs(G - ref).max() <= 2e-6 * scale
+    if ld is not None:
+        assert torch.all(out[..., 255:] == -7.0)
+    dense = sk.sigkernel_increment_gram(Xc, Yc, precision=precision).cpu().numpy()
+    assert np.array_equal(dense, G)
+
+
+@pytest.mark.parametrize("lx,ly", [(2, 2), (33, 5), (70, 130), (300, 34)])
+def test_row_stride_ragged_tiles(lx, ly):
+    # partial row blocks and partial column tiles at a padded stride
+    X = workloads.random_paths(410 + lx, 2, lx, 5)
+    Y = workloads.random_paths(420 + ly, 3, ly, 5)
+    n = ly - 1
+    ld = (n + 3) // 4 * 4 + 4
+    out = torch.full((2, 3, lx - 1, ld), -7.0, dtype=torch.float32, device="cuda")
+    G = sk.sigkernel_increment_gram(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(),
+                                    ld=ld, out=out).cpu().numpy()
+    ix, iy = rounded_increments(X, "f32"), rounded_increments(Y, "f32")
+    ref = np.einsum("apc,bqc->abpq", ix, iy)
+    scale = np.einsum("apc,bqc->abpq", np.abs(ix), np.abs(iy)).max()
+    assert np.abs(G - ref).max() <= 2e-6 * scale
+    assert torch.all(out[..., n:] == -7.0)
+
+
 def test_pairs_mode_matches_oracle_gram():
     X = workloads.random_paths(7, 4, 50, 5)
     Y = workloads.random_paths(8, 4, 31, 5)
