@@ -9,7 +9,9 @@ are resident in HBM before the timed region; every step recomputes everything.
 
 Prints ONE JSON line:
   value       grid-cell updates per second (whole job, one GPU)
-  roofline    the sweep kernel against the VALU issue rate
+  roofline    the sweep kernel against the FP64 VALU issue rate (3.125
+              FP64-equivalent operations per fine cell: two FP64 cell
+              operations and 9/4 FP32 FMAs counted at half an operation)
   cpu_baseline the FP64 oracle on the host cores, on a bounded sample
 """
 from __future__ import annotations

@@ -15,11 +15,11 @@
 // of the y tile; its half (l / 32) selects the channel slice.  Accumulator
 // register r of lane l holds row 8 (r / 4) + 4 (l / 32) + (r mod 4), column
 // l mod 32, and is stored from there: each store instruction writes 32
-// consecutive floats of two rows.  The kernel is bound by these stores; on
-// the 128 x 128 Gram of 256-point paths the forms measured are listed with
-// the design notes (whole-line 16-byte stores from a wave-private LDS
-// transpose, and whole rows written in order from a workgroup-wide block in
-// LDS, were not faster).
+// consecutive floats of two rows.  The kernel is bound by these stores.  On
+// the 128 x 128 Gram of 256-point paths (4.26 GB of G0) it takes 1.34 ms;
+// whole-line 16-byte stores from a wave-private LDS transpose took 1.39 ms,
+// whole rows written in order from the workgroup's block gathered in LDS
+// 1.53 ms, a 4-byte copy loop out of an LDS tile 1.88 ms.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
