@@ -98,7 +98,12 @@ __global__ __launch_bounds__(256) void pair_kernel(const PairArgs a) {
 #pragma unroll
       for (int cc = 0; cc < S; ++cc) pub[cc] = 1.0;
       double up_last = 1.0;
-      int32_t g = -lane;
+      // The top band's first off / R lanes hold only virtual rows: zero
+      // increments and the boundary value 1 whatever the step, so the band
+      // starts at the first real lane's first column (lane l at column
+      // t0 - l), saving those steps of pipeline fill.
+      const int32_t t0 = top ? off / R : 0;
+      int32_t g = t0 - lane;
       const float* __restrict__ yp = cinc + (int64_t)g * DP;
       // upper neighbours of lane 0: the boundary (top band) or the band above
       auto bnd_load = [&](int32_t t, double (&v)[S]) {
@@ -172,7 +177,9 @@ __global__ __launch_bounds__(256) void pair_kernel(const PairArgs a) {
         yp += DP;
       };
 
-      for (int32_t t = 0; t < nsteps; t += 3) {
+      // (from t0 the last iteration may run up to two steps past nsteps:
+      // inactive for every lane, rows within the stream padding)
+      for (int32_t t = t0; t < nsteps; t += 3) {
         step(t, dyA, dyC, bA, bC);
         step(t + 1, dyB, dyA, bB, bA);
         step(t + 2, dyC, dyB, bC, bB);
