@@ -15,9 +15,13 @@
 //     (float registers; nodes above the grid repeat x_0, which makes their
 //     coefficients exactly 0);
 //   * the wave streams y node rows; at node y_t a lane evaluates
-//     kappa(x_{p0+c}, y_t) for its CR+1 nodes in double (the differences of
-//     float coordinates are exact in double), and the row differences
-//     d_t[c] = kappa(x_{p0+c+1}, y_t) - kappa(x_{p0+c}, y_t); then
+//     kappa(x_{p0+c}, y_t) for its nodes c = 1 .. CR in double (the
+//     differences of float coordinates are exact in double); with at least
+//     2^lambda rows per lane its node 0 is lane l-1's node CR, which that
+//     lane evaluated at the previous step (one column ahead) with the same
+//     inputs and instructions, and arrives by DPP (with fewer rows, lanes
+//     share coarse rows and node 0 is evaluated too); then the row differences
+//     d_t[c] = kappa(x_{p0+c+1}, y_t) - kappa(x_{p0+c}, y_t) and
 //     G[p0+c][t-1] = d_t[c] - d_{t-1}[c];
 //   * each pair's stream starts with its node y_0, a priming step that only
 //     records d_0 (so a run of n_b-increment pairs takes sum (n_b + 1) steps).
@@ -63,7 +67,8 @@ __global__ __launch_bounds__(256) void lifted_sweep_kernel(const SweepArgs a) {
   const int M = m << LAM;
 
   // strips aligned to the bottom of the grid, as in the plain sweep
-  const int row0 = lane * R - (64 * R - M);
+  const int off = 64 * R - M;  // virtual rows above row 0 (uniform)
+  const int row0 = lane * R - off;
   const int p0 = row0 >> LAM;
   const int64_t xnode = first_node(a.x_start, a.x_len, ia);
   float xn[CR + 1][D];
@@ -99,6 +104,13 @@ __global__ __launch_bounds__(256) void lifted_sweep_kernel(const SweepArgs a) {
   double dprev[CR];
 #pragma unroll
   for (int c = 0; c < CR; ++c) dprev[c] = 0.0;
+  // this lane's node-CR kernel value at the previous step, for lane l+1
+  // (R >= 2^lambda: lane l's first coarse row is lane l-1's last plus one)
+  double kpub = 0.0;
+  // Lane 0 has no lane above: when its strip starts above the grid (off > 0)
+  // its nodes 0 and 1 are both x_0 and node 1's value serves; when the grid
+  // fills the wave exactly, node 0 is evaluated as well (a uniform branch).
+  const bool own_top = off == 0;
 
   float yA[DP], yB[DP], yC[DP];
   load_row<DP>(yp, yA);
@@ -110,16 +122,25 @@ __global__ __launch_bounds__(256) void lifted_sweep_kernel(const SweepArgs a) {
     double yd[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) yd[k] = (double)yn[k];
-    double kap[CR + 1];
-#pragma unroll
-    for (int c = 0; c <= CR; ++c) {
+    auto kappa = [&](int c) {
       double r = 0.0;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         const double t = (double)xn[c][k] - yd[k];
         r = __builtin_fma(t, t, r);
       }
-      kap[c] = exp(-r * inv);
+      return exp(-r * inv);
+    };
+    double kap[CR + 1];
+#pragma unroll
+    for (int c = 1; c <= CR; ++c) kap[c] = kappa(c);
+    if constexpr (R >= S) {
+      double keep0 = kap[1];
+      if (own_top) keep0 = kappa(0);
+      kap[0] = from_prev_lane(kpub, keep0);
+      kpub = kap[CR];
+    } else {
+      kap[0] = kappa(0);  // lanes share coarse rows: no lane above holds node 0
     }
 
 #pragma unroll

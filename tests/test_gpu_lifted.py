@@ -116,6 +116,18 @@ def test_tallest_compiled_x_path():
         sk.sigkernel_gram_lifted(cuda(X), cuda(Y), 1, sigma=0.3)
 
 
+@pytest.mark.parametrize("L", [200, 256, 257])
+def test_top_lane_node_when_the_grid_fills_the_wave(L):
+    # a lane takes its top node's kernel value from the lane above; lane 0
+    # evaluates it itself only when the x grid fills the wave exactly (257
+    # points at order 1: 512 fine rows, 8 per lane), else it reuses its own
+    # node 1 (both are x_0 above the grid)
+    X = workloads.random_paths(240 + L, 2, L, 4)
+    Y = workloads.random_paths(250 + L, 3, 90, 4)
+    K = sk.sigkernel_gram_lifted(cuda(X), cuda(Y), 1, sigma=0.7).cpu().numpy()
+    assert mixed_err(K, oracle.lifted_rbf_gram(f64(X), f64(Y), 1, 0.7)).max() <= TOL
+
+
 def test_linear_static_kernel_is_the_plain_call():
     X = workloads.random_paths(230, 6, 40, 3)
     Y = workloads.random_paths(231, 5, 30, 3)
