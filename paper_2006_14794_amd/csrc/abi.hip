@@ -644,6 +644,10 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam0, uint32
     a.run = Y->offsets ? 1 : (int32_t)choose_run(X->n_paths, Y->n_paths, tune.run);
     a.runs_per_row = (Y->n_paths + a.run - 1) / a.run;
     a.n_waves = X->n_paths * a.runs_per_row;
+    if (mode == 2) {  // only the runs of the upper triangle
+      a.tri = 1;
+      a.n_waves = sk::tri_runs(X->n_paths, a.runs_per_row, a.run);
+    }
   }
   const hipError_t e = sk::launch_sweep(a, lam, R, d, stream, tune.waves_per_block);
   if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;
@@ -878,6 +882,10 @@ sk_status run_lifted(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t
     a.run = Y->offsets ? 1 : (int32_t)choose_run(X->n_paths, Y->n_paths, 0);
     a.runs_per_row = (Y->n_paths + a.run - 1) / a.run;
     a.n_waves = X->n_paths * a.runs_per_row;
+    if (mode == 2) {  // only the runs of the upper triangle
+      a.tri = 1;
+      a.n_waves = sk::tri_runs(X->n_paths, a.runs_per_row, a.run);
+    }
   }
   const hipError_t e = sk::launch_lifted(a, lam, R, d, stream, 0);
   if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;

@@ -26,6 +26,7 @@ struct SweepArgs {
   double lift_scale;        // lifted sweep: 2^-(2 lam + 1), the coefficient's fine-cell factor
   int32_t run;              // pairs streamed through one wave (Gram with uniform y)
   int64_t runs_per_row;     // ceil(ny / run)
+  int32_t tri;              // mode 2: waves enumerate only the runs that hold pairs (tri_runs)
   int64_t n_waves;
   float* out;               // nullptr: terminal values not written
   int64_t out_ld;           // ny for the Gram
@@ -47,6 +48,17 @@ constexpr int64_t kStreamPad = 128;
 // the y-row prefetch rotates three buffers).
 __host__ __device__ inline int64_t sweep_steps(int64_t total) {
   return ((total + 63 + 2) / 3) * 3;
+}
+
+// The upper triangle of a symmetric Gram by runs: row i (x_i) has runs of
+// y columns starting at multiples of `run`, the one holding column i
+// clipped to start there, so it holds runs_per_row - floor(i / run) runs.
+// Waves enumerated over these alone (no wave without a pair) are spread
+// evenly over the compute units; tri_runs(i) counts the runs of rows
+// 0 .. i-1.
+__host__ __device__ inline int64_t tri_runs(int64_t i, int64_t runs_per_row, int64_t run) {
+  const int64_t q = i / run, r = i - q * run;
+  return i * runs_per_row - (run * q * (q - 1) / 2 + q * r);
 }
 
 }  // namespace sk

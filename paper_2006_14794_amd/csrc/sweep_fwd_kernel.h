@@ -148,6 +148,17 @@ __device__ __forceinline__ bool wave_run(const SweepArgs& a, int64_t w, int lane
     ia = w;
     b0 = w;
     b1 = w + 1;
+  } else if (a.tri) {
+    // the last row whose runs start at or before wave w (binary search on
+    // the increasing run counts; the values are uniform over the wave)
+    int64_t lo = 0, hi = a.nx;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (tri_runs(mid, a.runs_per_row, a.run) <= w) lo = mid; else hi = mid;
+    }
+    ia = lo;
+    b0 = (ia / a.run + (w - tri_runs(ia, a.runs_per_row, a.run))) * a.run;
+    b1 = b0 + a.run < a.ny ? b0 + a.run : a.ny;
   } else {
     ia = w / a.runs_per_row;
     b0 = (w - ia * a.runs_per_row) * a.run;
