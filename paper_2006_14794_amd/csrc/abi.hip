@@ -300,6 +300,20 @@ struct GradPlan {
   size_t order, counts, scratch, partx, party, total;
 };
 
+// Pairs per gradient task for a uniform y batch: the tuned value, else about
+// one task with pairs per persistent wave (kGradSlots; a symmetric Gram's
+// tasks below the diagonal are empty), at most 64 pairs per task.  Longer
+// tasks pay the wavefront's fill once per run of pairs instead of per pair.
+int64_t choose_grad_run(int64_t nx, int64_t ny, bool sym, int32_t tuned) {
+  if (tuned > 0) return tuned < ny ? tuned : (ny > 0 ? ny : 1);
+  const int64_t pairs = sym ? nx * (nx + 1) / 2 : nx * ny;
+  int64_t run = pairs / kGradSlots;
+  if (run < 1) run = 1;
+  if (run > 64) run = 64;
+  if (run > ny) run = ny;
+  return run;
+}
+
 GradPlan grad_plan(const sk_paths* X0, const sk_paths* Y0, int32_t lam0, uint32_t flags) {
   const Order o = split_order(lam0);
   const sk_paths Xr = refined(X0, o.rep), Yr = refined(Y0, o.rep);
@@ -316,7 +330,7 @@ GradPlan grad_plan(const sk_paths* X0, const sk_paths* Y0, int32_t lam0, uint32_
     P.runs_per_row = Y0->n_paths;
   } else {
     const sk_tune t = sk::tuning_for(SK_OP_GRAM_BACKWARD, X0, Y0, lam0, flags);
-    P.run = choose_run(X0->n_paths, Y0->n_paths, t.run);
+    P.run = choose_grad_run(X0->n_paths, Y0->n_paths, (flags & SK_SYMMETRIC) != 0, t.run);
     P.runs_per_row = (Y0->n_paths + P.run - 1) / P.run;
   }
   P.n_tasks = X0->n_paths * P.runs_per_row;
