@@ -110,12 +110,13 @@ ForwardLayout forward_layout(const sk_paths* X, const sk_paths* Y) {
 size_t forward_ws(const sk_paths* X, const sk_paths* Y) { return forward_layout(X, Y).total; }
 
 // Pairs streamed through one wave for a Gram with a uniform y batch: the
-// tuned value, else enough waves to fill every SIMD about four times, at
-// most 64 pairs per run.
-int64_t choose_run(int64_t nx, int64_t ny, int32_t tuned) {
+// tuned value, else enough waves to fill every SIMD about four times (a
+// symmetric Gram counts the pairs of its upper triangle), at most 64 pairs
+// per run.
+int64_t choose_run(int64_t nx, int64_t ny, int32_t tuned, bool sym = false) {
   if (tuned > 0) return tuned < ny ? tuned : (ny > 0 ? ny : 1);
   const int64_t target_waves = 256 * 4 * 4;
-  int64_t run = (nx * ny) / target_waves;
+  int64_t run = (sym ? nx * (nx + 1) / 2 : nx * ny) / target_waves;
   if (run < 1) run = 1;
   if (run > 64) run = 64;
   if (run > ny) run = ny;
@@ -655,7 +656,7 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam0, uint32
     a.runs_per_row = 1;
     a.n_waves = X->n_paths;
   } else {
-    a.run = Y->offsets ? 1 : (int32_t)choose_run(X->n_paths, Y->n_paths, tune.run);
+    a.run = Y->offsets ? 1 : (int32_t)choose_run(X->n_paths, Y->n_paths, tune.run, mode == 2);
     a.runs_per_row = (Y->n_paths + a.run - 1) / a.run;
     a.n_waves = X->n_paths * a.runs_per_row;
     if (mode == 2) {  // only the runs of the upper triangle
@@ -893,7 +894,7 @@ sk_status run_lifted(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t
     a.runs_per_row = 1;
     a.n_waves = X->n_paths;
   } else {
-    a.run = Y->offsets ? 1 : (int32_t)choose_run(X->n_paths, Y->n_paths, 0);
+    a.run = Y->offsets ? 1 : (int32_t)choose_run(X->n_paths, Y->n_paths, 0, mode == 2);
     a.runs_per_row = (Y->n_paths + a.run - 1) / a.run;
     a.n_waves = X->n_paths * a.runs_per_row;
     if (mode == 2) {  // only the runs of the upper triangle
