@@ -110,17 +110,55 @@ ForwardLayout forward_layout(const sk_paths* X, const sk_paths* Y) {
 size_t forward_ws(const sk_paths* X, const sk_paths* Y) { return forward_layout(X, Y).total; }
 
 // Pairs streamed through one wave for a Gram with a uniform y batch: the
-// tuned value, else enough waves to fill every SIMD about four times (a
-// symmetric Gram counts the pairs of its upper triangle), at most 64 pairs
-// per run.
-int64_t choose_run(int64_t nx, int64_t ny, int32_t tuned, bool sym = false) {
+// tuned value, else enough waves to fill every SIMD about four times, at
+// most 64 pairs per run.
+int64_t choose_run(int64_t nx, int64_t ny, int32_t tuned) {
   if (tuned > 0) return tuned < ny ? tuned : (ny > 0 ? ny : 1);
   const int64_t target_waves = 256 * 4 * 4;
-  int64_t run = (sym ? nx * (nx + 1) / 2 : nx * ny) / target_waves;
+  int64_t run = (nx * ny) / target_waves;
   if (run < 1) run = 1;
   if (run > 64) run = 64;
   if (run > ny) run = ny;
   return run;
+}
+
+// SIMDs of the current device (four per compute unit); 1024 if unknown.
+int64_t device_simds() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    return 1024;
+  return 4 * (int64_t)cus;
+}
+
+// Pairs streamed through one wave of a one-wave forward Gram sweep: the tuned
+// value, else the run that minimises the busiest SIMD's time.  A run of k
+// pairs over `cols` fine columns each takes about k + 64 / cols pair times
+// (the wavefront fills once per run); the busiest SIMD holds
+// ceil(waves / SIMDs) waves, and a SIMD with one, two or three waves issues
+// at 0.73, 0.93 or 0.97 of its rate with four or more (measured on the
+// sweep).  A symmetric Gram counts only its upper triangle's runs.  At most
+// 64 pairs per run; ties go to the shorter run.
+int64_t choose_sweep_run(int64_t nx, int64_t ny, int64_t cols, bool sym, int32_t tuned) {
+  if (tuned > 0 || ny <= 1 || cols <= 0) return choose_run(nx, ny, tuned);
+  const int64_t simds = device_simds();
+  const double fill = 64.0 / (double)cols;
+  const int64_t cap = ny < 64 ? ny : 64;
+  int64_t best = 1;
+  double best_cost = 0.0;
+  for (int64_t run = 1; run <= cap; ++run) {
+    const int64_t rpr = (ny + run - 1) / run;
+    const int64_t waves = sym ? sk::tri_runs(nx, rpr, run) : nx * rpr;
+    const int64_t per_simd = (waves + simds - 1) / simds;
+    const double rate = per_simd >= 4 ? 1.0 : per_simd == 3 ? 0.97 : per_simd == 2 ? 0.93 : 0.73;
+    const double cost = (double)per_simd * ((double)run + fill) / rate;
+    if (run == 1 || cost < best_cost) {
+      best = run;
+      best_cost = cost;
+    }
+  }
+  return best;
 }
 
 // Independent pairs: the forward layout (increments not scaled), the pair
@@ -656,7 +694,10 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam0, uint32
     a.runs_per_row = 1;
     a.n_waves = X->n_paths;
   } else {
-    a.run = Y->offsets ? 1 : (int32_t)choose_run(X->n_paths, Y->n_paths, tune.run, mode == 2);
+    a.run = Y->offsets ? 1
+                       : (int32_t)choose_sweep_run(X->n_paths, Y->n_paths,
+                                                   (int64_t)(Y->len - 1) << lam, mode == 2,
+                                                   tune.run);
     a.runs_per_row = (Y->n_paths + a.run - 1) / a.run;
     a.n_waves = X->n_paths * a.runs_per_row;
     if (mode == 2) {  // only the runs of the upper triangle
@@ -894,7 +935,9 @@ sk_status run_lifted(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t
     a.runs_per_row = 1;
     a.n_waves = X->n_paths;
   } else {
-    a.run = Y->offsets ? 1 : (int32_t)choose_run(X->n_paths, Y->n_paths, 0, mode == 2);
+    a.run = Y->offsets ? 1
+                       : (int32_t)choose_sweep_run(X->n_paths, Y->n_paths,
+                                                   (int64_t)(Y->len - 1) << lam, mode == 2, 0);
     a.runs_per_row = (Y->n_paths + a.run - 1) / a.run;
     a.n_waves = X->n_paths * a.runs_per_row;
     if (mode == 2) {  // only the runs of the upper triangle
