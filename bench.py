@@ -61,7 +61,7 @@ def parse():
                          "pair: one 32-point pair in R^2 at order 0 (latency per call); "
                          "mmd: unbiased MMD^2 of 64 vs 64 512-point paths with its gradient; "
                          "ragged: 4096 independent pairs of uneven lengths; "
-                         "increment_gram: the coarse Gram of the Gram batch on the matrix cores; "
+                         "increment_gram: the coarse Gram of the Gram batch written to HBM; "
                          "corrector: order-3 values of 65536 held-out pairs by the learned "
                          "corrector with fallback, against the plain order-3 solve; "
                          "lifted: the RBF-lifted Gram (sigma 0.5) of the Gram batch; "
@@ -608,7 +608,7 @@ def bench_reduce(args):
 
 def bench_increment_gram(args):
     """The coarse increment Gram G0 of the 128 x 128 Gram batch (255 x 255 per
-    pair, d = 9) on the matrix cores, written to HBM: bound by the 4-byte
+    pair, d = 9) written to HBM row after row: bound by the 4-byte
     write per coarse cell.  Timed in the dense layout and with rows padded
     to 256 floats (1 KB); the bytes counted are G0's own (the padding column
     is not written) plus the points read."""

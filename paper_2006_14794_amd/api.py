@@ -423,7 +423,7 @@ def mmd2(X: torch.Tensor, Y: torch.Tensor, dyadic_order: int = 0) -> torch.Tenso
 def sigkernel_increment_gram(X: torch.Tensor, Y: torch.Tensor, *, gram: bool = True,
                              precision: str = "f32", ld: Optional[int] = None,
                              out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """G0 = <x_{p+1} - x_p, y_{q+1} - y_q> of every pair on the matrix cores:
+    """G0 = <x_{p+1} - x_p, y_{q+1} - y_q> of every pair (float32 VALU, rows in order):
     [nx, ny, Lx-1, Ly-1] (gram) or [n, Lx-1, Ly-1] (pairs).  ``ld`` (>= Ly-1)
     stores each row with that stride: ``out`` then has ld columns, of which
     the first Ly-1 are written and returned as a view."""

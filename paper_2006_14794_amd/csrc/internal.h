@@ -235,7 +235,8 @@ struct ReduceArgs {
 };
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream);
 
-// Increment Gram of uniform batches on the matrix cores (gram_mfma.hip).
+// Increment Gram of uniform batches (gram_rows.hip): float32 VALU, rows written
+// in order; d at most kGramRowsMaxDim.
 struct GramArgs {
   const float* x;           // points [nx][x_len][d]
   const float* y;           // points [ny][y_len][d]
@@ -245,8 +246,9 @@ struct GramArgs {
   float* g0;                // [pairs][x_len - 1][ld], columns < y_len - 1 written
   int64_t ld;               // row stride of g0 in floats, >= y_len - 1
 };
-// precision: kRoundNone (float32 MFMA), kRoundBf16, kRoundF16
-hipError_t launch_gram_mfma(const GramArgs& a, int precision, hipStream_t stream);
+// precision: kRoundNone (float32 inputs), kRoundBf16, kRoundF16
+constexpr int kGramRowsMaxDim = 16;
+hipError_t launch_gram_rows(const GramArgs& a, int precision, hipStream_t stream);
 
 // Compiled sweep kernels by kind, dyadic order, rows per lane and channels
 // (nullptr when the configuration is not compiled).

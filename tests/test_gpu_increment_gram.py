@@ -1,4 +1,4 @@
-"""Coarse increment Gram on the matrix cores (sigkernel_increment_gram) and the
+"""Coarse increment Gram written to HBM (sigkernel_increment_gram) and the
 16-bit-input option of the sweeps, against the FP64 oracle.
 
 References for 16-bit inputs round the float32 increments to bfloat16 / half
@@ -148,3 +148,20 @@ def test_sixteen_bit_ragged_match_rounded_paths(precision):
     ref = oracle.pairs([rounded_paths(a, precision) for a in xs],
                        [rounded_paths(b, precision) for b in ys], 2)
     assert mixed_err(got, ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("d,lx,ly", [(2, 2, 700), (7, 4, 513), (16, 66, 258), (5, 129, 257),
+                                     (3, 5, 1030), (11, 200, 3)])
+def test_row_blocks_and_column_chunks(precision, d, lx, ly):
+    # 64-row blocks with fewer rows than waves, a last block of 1-3 rows per
+    # wave, rows of several 256-column chunks with a ragged last chunk
+    X = workloads.random_paths(500 + lx, 2, lx, d)
+    Y = workloads.random_paths(600 + ly, 3, ly, d)
+    G = sk.sigkernel_increment_gram(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(),
+                                    precision=precision).cpu().numpy()
+    ix, iy = rounded_increments(X, precision), rounded_increments(Y, precision)
+    ref = np.einsum("apc,bqc->abpq", ix, iy)
+    scale = np.einsum("apc,bqc->abpq", np.abs(ix), np.abs(iy)).max()
+    assert G.shape == ref.shape
+    assert np.abs(G - ref).max() <= 2e-6 * scale
