@@ -188,13 +188,14 @@ sk_status sigkernel_gram_backward(const sk_paths *X, const sk_paths *Y, int32_t 
 
 /*
  * sigkernel_increment_gram -- the coarse increment inner products of Section
- * 3.1 (piecewise-linear case), on the vector ALUs with rows written in order
- * (at most 16 channels the contraction is far from paying for the matrix
- * cores; the writes bound it):
+ * 3.1 (piecewise-linear case): up to 16 channels on the vector ALUs with rows
+ * written in order (the contraction is too short to pay for the matrix cores;
+ * the writes bound it), 17 to 64 channels on the matrix cores in 32 x 32
+ * tiles:
  *   G0[pair][p][q] = <x_{p+1} - x_p, y_{q+1} - y_q>,  p < x.len - 1, q < y.len - 1,
  * written to HBM for every pair: gram = 1 enumerates (a, b) as a * Y->n_paths
  * + b, gram = 0 the pairs (x_k, y_k) (equal batch sizes).
- *  - Uniform batches of at most 16 channels; G0: DEVICE
+ *  - Uniform batches of at most 64 channels (more: SK_ERR_UNSUPPORTED); G0: DEVICE
  *    float[pairs][X->len - 1][ldg], of which columns q < Y->len - 1 are
  *    written (the rest of each row is left as it was).  ldg = 0 means the
  *    dense layout, ldg = Y->len - 1; a nonzero ldg below that gives
@@ -203,8 +204,9 @@ sk_status sigkernel_gram_backward(const sk_paths *X, const sk_paths *Y, int32_t 
  *    untouched padding leaves the last cache line of every row partly
  *    written.
  *  - flags: SK_GRAM_BF16 / SK_GRAM_F16 round the increments to 16 bits (the
- *    products and sums stay float32); otherwise float32 throughout.  Each
- *    entry is summed channel by channel in order with fused multiply-adds.
+ *    products and sums stay float32); otherwise float32 throughout.  Up to 16
+ *    channels each entry is summed channel by channel in order with fused
+ *    multiply-adds; above that the matrix cores choose the summation order.
  *  - No workspace.  Paths with one point give an empty G0 (nothing written).
  * The sweeps of sigkernel_pair / sigkernel_gram do not read G0 from memory:
  * they form the same inner products on the fly in registers, which avoids

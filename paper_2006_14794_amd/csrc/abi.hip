@@ -1197,7 +1197,7 @@ sk_status sigkernel_increment_gram(const sk_paths* X, const sk_paths* Y, int32_t
   const int64_t pairs = gram ? X->n_paths * Y->n_paths : X->n_paths;
   if (pairs == 0 || X->len < 2 || Y->len < 2) return SK_OK;
   if (!G0 || !X->points || !Y->points) return SK_ERR_NULL;
-  if (X->dim > sk::kGramRowsMaxDim) return SK_ERR_UNSUPPORTED;
+  if (X->dim > sk::kGramMfmaMaxDim) return SK_ERR_UNSUPPORTED;
   sk::GramArgs a{};
   a.x = X->points;
   a.y = Y->points;
@@ -1209,8 +1209,9 @@ sk_status sigkernel_increment_gram(const sk_paths* X, const sk_paths* Y, int32_t
   a.gram = gram;
   a.g0 = G0;
   a.ld = ldg ? ldg : (int64_t)Y->len - 1;
-  const hipError_t e =
-      sk::launch_gram_rows(a, rounding_of(flags), static_cast<hipStream_t>(stream));
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipError_t e = X->dim <= sk::kGramRowsMaxDim ? sk::launch_gram_rows(a, rounding_of(flags), st)
+                                                     : sk::launch_gram_mfma(a, rounding_of(flags), st);
   if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;
   return e == hipSuccess ? SK_OK : SK_ERR_HIP;
 }

@@ -37,6 +37,10 @@ namespace {
 
 constexpr int kCols = 256;        // columns per wave: four per lane
 constexpr int kRowsPerWave = 16;  // every fourth row of a 64-row block
+// LDS row stride of the staged y points: odd, so that the lanes' rows (one
+// column per lane) fall in distinct banks
+template <int D>
+constexpr int kYStride = D | 1;
 
 template <int PREC>  // 0: float32, 1: bf16, 2: fp16
 __device__ __forceinline__ float round_input(float v) {
@@ -48,7 +52,7 @@ __device__ __forceinline__ float round_input(float v) {
 template <int PREC, int D>
 __global__ __launch_bounds__(256) void gram_rows_kernel(const GramArgs a, int32_t row_groups,
                                                          int32_t col_chunks) {
-  __shared__ float ys[(kCols + 1) * D];              // the chunk's points
+  __shared__ float ys[(kCols + 1) * kYStride<D>];   // the chunk's points
   __shared__ float xs_all[4][kRowsPerWave * D];      // each wave's x increments
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -65,7 +69,10 @@ __global__ __launch_bounds__(256) void gram_rows_kernel(const GramArgs a, int32_
   const int32_t cw = n - cbase < kCols ? n - cbase : kCols;
 
   const float* __restrict__ yq = a.y + (ib * (int64_t)a.y_len + cbase) * D;
-  for (int32_t e = threadIdx.x; e < (cw + 1) * D; e += 256) ys[e] = yq[e];
+  for (int32_t e = threadIdx.x; e < (cw + 1) * D; e += 256) {
+    const int32_t r = e / D;
+    ys[r * kYStride<D> + (e - r * D)] = yq[e];
+  }
   __syncthreads();  // the only barrier: waves without rows may leave after it
 
   // the wave's rows: p0 + 4 i for i < nr
@@ -81,7 +88,8 @@ __global__ __launch_bounds__(256) void gram_rows_kernel(const GramArgs a, int32_
     const bool ok = c < cw;
 #pragma unroll
     for (int k = 0; k < D; ++k)
-      dy[j][k] = ok ? round_input<PREC>(ys[(c + 1) * D + k] - ys[c * D + k]) : 0.0f;
+      dy[j][k] = ok ? round_input<PREC>(ys[(c + 1) * kYStride<D> + k] - ys[c * kYStride<D> + k])
+                    : 0.0f;
   }
 
   // the wave's x increments, [i][k]

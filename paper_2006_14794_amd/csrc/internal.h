@@ -235,8 +235,7 @@ struct ReduceArgs {
 };
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream);
 
-// Increment Gram of uniform batches (gram_rows.hip): float32 VALU, rows written
-// in order; d at most kGramRowsMaxDim.
+// Increment Gram of uniform batches.
 struct GramArgs {
   const float* x;           // points [nx][x_len][d]
   const float* y;           // points [ny][y_len][d]
@@ -249,6 +248,10 @@ struct GramArgs {
 // precision: kRoundNone (float32 inputs), kRoundBf16, kRoundF16
 constexpr int kGramRowsMaxDim = 16;
 hipError_t launch_gram_rows(const GramArgs& a, int precision, hipStream_t stream);
+// The same on the matrix cores for kGramRowsMaxDim < d <= kGramMfmaMaxDim
+// (gram_mfma.hip).
+constexpr int kGramMfmaMaxDim = 64;
+hipError_t launch_gram_mfma(const GramArgs& a, int precision, hipStream_t stream);
 
 // Compiled sweep kernels by kind, dyadic order, rows per lane and channels
 // (nullptr when the configuration is not compiled).

@@ -194,6 +194,15 @@ def test_increment_gram_row_stride_below_the_row_length_is_a_shape_error():
                                             None) == _lib.SK_ERR_SHAPE
 
 
+def test_increment_gram_channel_limit():
+    # up to 64 channels (16 on the vector ALUs, 17-64 on the matrix cores);
+    # more is refused before anything is enqueued
+    lib = _lib.load()
+    X, Y = paths(d=65), paths(d=65)
+    assert lib.sigkernel_increment_gram(ctypes.byref(X), ctypes.byref(Y), 1, 0, FAKE, 0,
+                                        None) == _lib.SK_ERR_UNSUPPORTED
+
+
 def call_lifted(fn, X, Y, kernel, lam=1, flags=0, out=FAKE, ws=FAKE, nbytes=1 << 30):
     lib = _lib.load()
     return getattr(lib, fn)(ctypes.byref(X), ctypes.byref(Y), lam, flags,

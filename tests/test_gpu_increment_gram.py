@@ -165,3 +165,31 @@ def test_row_blocks_and_column_chunks(precision, d, lx, ly):
     scale = np.einsum("apc,bqc->abpq", np.abs(ix), np.abs(iy)).max()
     assert G.shape == ref.shape
     assert np.abs(G - ref).max() <= 2e-6 * scale
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("d,lx,ly", [(17, 40, 33), (24, 70, 129), (33, 33, 300), (64, 97, 65),
+                                     (40, 2, 2), (64, 258, 131)])
+def test_matrix_core_channels(precision, d, lx, ly):
+    # 17-64 channels go to the 32 x 32 MFMA tiles: partial row blocks, partial
+    # column tiles and chunks, odd channel counts (a zero-padded last slice);
+    # the bound is float32 summation of d products in any order
+    X = workloads.random_paths(700 + d, 3, lx, d)
+    Y = workloads.random_paths(800 + d, 2, ly, d)
+    G = sk.sigkernel_increment_gram(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(),
+                                    precision=precision).cpu().numpy()
+    ix, iy = rounded_increments(X, precision), rounded_increments(Y, precision)
+    ref = np.einsum("apc,bqc->abpq", ix, iy)
+    scale = np.einsum("apc,bqc->abpq", np.abs(ix), np.abs(iy)).max()
+    assert G.shape == ref.shape
+    assert np.abs(G - ref).max() <= d * 2.0 ** -23 * scale
+
+
+def test_matrix_core_row_stride():
+    X = workloads.random_paths(900, 2, 70, 20)
+    Y = workloads.random_paths(901, 3, 50, 20)
+    Xc, Yc = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    out = torch.full((2, 3, 69, 53), -7.0, dtype=torch.float32, device="cuda")
+    G = sk.sigkernel_increment_gram(Xc, Yc, ld=53, out=out).cpu().numpy()
+    assert torch.all(out[..., 49:] == -7.0)
+    assert np.array_equal(G, sk.sigkernel_increment_gram(Xc, Yc).cpu().numpy())
