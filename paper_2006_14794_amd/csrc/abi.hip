@@ -435,11 +435,9 @@ sk_status run_pairs(const sk_paths* X, const sk_paths* Y, int32_t lam0, float* o
   const sk::Batch bx = to_batch(X), by = to_batch(Y);
   if (X->offsets && sk::launch_plan(bx, px, stream) != hipSuccess) return SK_ERR_HIP;
   if (Y->offsets && sk::launch_plan(by, py, stream) != hipSuccess) return SK_ERR_HIP;
-  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, 1.0f, dp, incx, stream, rounding,
-                            o.rep) != hipSuccess)
-    return SK_ERR_HIP;
-  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream, rounding,
-                            o.rep) != hipSuccess)
+  if (sk::launch_increments_xy(bx, X->offsets ? &px : nullptr, 1.0f, by,
+                               Y->offsets ? &py : nullptr, 1.0f, dp, incx, incy, stream, rounding,
+                               o.rep) != hipSuccess)
     return SK_ERR_HIP;
   if (X->offsets && sk::launch_scale_plan(px, X->n_paths, o.rep, stream) != hipSuccess)
     return SK_ERR_HIP;
@@ -551,11 +549,9 @@ sk_status run_coef(const sk_paths* X, const sk_paths* Y, int32_t lam0, uint32_t 
   if (X->offsets && sk::launch_plan(bx, px, stream) != hipSuccess) return SK_ERR_HIP;
   if (Y->offsets && sk::launch_plan(by, py, stream) != hipSuccess) return SK_ERR_HIP;
   const int rounding = rounding_of(flags);
-  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, 1.0f, dp, incx, stream, rounding) !=
-      hipSuccess)
-    return SK_ERR_HIP;
-  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream, rounding) !=
-      hipSuccess)
+  if (sk::launch_increments_xy(bx, X->offsets ? &px : nullptr, 1.0f, by,
+                               Y->offsets ? &py : nullptr, 1.0f, dp, incx, incy, stream,
+                               rounding) != hipSuccess)
     return SK_ERR_HIP;
   // both kernels see the refined counts (the producer divides them back)
   if (X->offsets && sk::launch_scale_plan(px, X->n_paths, P.rep, stream) != hipSuccess)
@@ -662,11 +658,9 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam0, uint32
   if (Y->offsets && sk::launch_plan(by, py, stream) != hipSuccess) return SK_ERR_HIP;
   // h = G0 / 2^(2 lam + 1): fold the exact power-of-two scale into the x side
   const float scale = ldexpf(1.0f, -(2 * lam + 1));
-  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, scale, dp, incx, stream, rounding,
-                            o.rep) != hipSuccess)
-    return SK_ERR_HIP;
-  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, stream, rounding,
-                            o.rep) != hipSuccess)
+  if (sk::launch_increments_xy(bx, X->offsets ? &px : nullptr, scale, by,
+                               Y->offsets ? &py : nullptr, 1.0f, dp, incx, incy, stream, rounding,
+                               o.rep) != hipSuccess)
     return SK_ERR_HIP;
   if (X->offsets && sk::launch_scale_plan(px, X->n_paths, o.rep, stream) != hipSuccess)
     return SK_ERR_HIP;
@@ -816,9 +810,8 @@ sk_status corrector_increments(const sk_paths* X, const sk_paths* Y, char* base,
   const ForwardLayout L = forward_layout(X, Y);
   *incx = reinterpret_cast<float*>(base + L.incx) + sk::kStreamPad * dp;
   *incy = reinterpret_cast<float*>(base + L.incy) + sk::kStreamPad * dp;
-  if (sk::launch_increments(to_batch(X), nullptr, 1.0f, dp, *incx, st) != hipSuccess)
-    return SK_ERR_HIP;
-  if (sk::launch_increments(to_batch(Y), nullptr, 1.0f, dp, *incy, st) != hipSuccess)
+  if (sk::launch_increments_xy(to_batch(X), nullptr, 1.0f, to_batch(Y), nullptr, 1.0f, dp, *incx,
+                               *incy, st) != hipSuccess)
     return SK_ERR_HIP;
   return SK_OK;
 }
@@ -1337,11 +1330,9 @@ static sk_status gram_backward(const sk_paths* X, const sk_paths* Y, int32_t dya
   const float scale = ldexpf(1.0f, -(2 * lam + 1));
   if (X->offsets && sk::launch_plan(bx, px, st) != hipSuccess) return SK_ERR_HIP;
   if (Y->offsets && sk::launch_plan(by, py, st) != hipSuccess) return SK_ERR_HIP;
-  if (sk::launch_increments(bx, X->offsets ? &px : nullptr, scale, dp, incx, st,
-                            sk::kRoundNone, o.rep) != hipSuccess)
-    return SK_ERR_HIP;
-  if (sk::launch_increments(by, Y->offsets ? &py : nullptr, 1.0f, dp, incy, st, sk::kRoundNone,
-                            o.rep) != hipSuccess)
+  if (sk::launch_increments_xy(bx, X->offsets ? &px : nullptr, scale, by,
+                               Y->offsets ? &py : nullptr, 1.0f, dp, incx, incy, st, sk::kRoundNone,
+                               o.rep) != hipSuccess)
     return SK_ERR_HIP;
   if (X->offsets && sk::launch_scale_plan(px, X->n_paths, o.rep, st) != hipSuccess)
     return SK_ERR_HIP;

@@ -53,21 +53,34 @@ __global__ __launch_bounds__(1024) void plan_kernel(const int64_t* __restrict__ 
   }
 }
 
-// One workgroup per path: dense rows [start, start + n) of the output.
-__global__ __launch_bounds__(256) void increments_kernel(
-    const float* __restrict__ pts, const int64_t* __restrict__ off,
-    const int32_t* __restrict__ plan_n, const int64_t* __restrict__ plan_start, int32_t len,
-    int64_t n_paths, int32_t d, int32_t dpad, float scale, int32_t rounding, int32_t rep,
-    float* __restrict__ incr) {
-  const int64_t k = blockIdx.x;
-  if (k >= n_paths) return;
+// The increments of one batch (the two batches of a call go in one launch).
+struct IncJob {
+  const float* pts;
+  const int64_t* off;        // ragged offsets, or null
+  const int32_t* plan_n;     // ragged plan
+  const int64_t* plan_start;
+  int32_t len;
+  int64_t n_paths;
+  int32_t d, dpad;
+  float scale;               // includes 1 / rep
+  int32_t rounding, rep;
+  float* incr;
+};
+
+// Path k of a job: one workgroup writes its dense rows [start, start + n).
+__device__ __forceinline__ void increments_one(const IncJob& j, int64_t k) {
+  const float* __restrict__ pts = j.pts;
+  const int64_t* __restrict__ off = j.off;
+  const int32_t len = j.len, d = j.d, dpad = j.dpad, rounding = j.rounding, rep = j.rep;
+  const float scale = j.scale;
+  float* __restrict__ incr = j.incr;
   int64_t pstart, dstart;
   int32_t n;
   if (off) {
-    n = plan_n[k];
+    n = j.plan_n[k];
     if (n <= 0) return;
     pstart = off[k];
-    dstart = plan_start[k] * rep;
+    dstart = j.plan_start[k] * rep;
   } else {
     n = len - 1;
     pstart = k * (int64_t)len;
@@ -105,6 +118,15 @@ __global__ __launch_bounds__(256) void increments_kernel(
   }
 }
 
+// Workgroups [0, jx.n_paths) take the paths of jx, the rest those of jy.
+__global__ __launch_bounds__(256) void increments_kernel(const IncJob jx, const IncJob jy) {
+  const int64_t b = blockIdx.x;
+  if (b < jx.n_paths)
+    increments_one(jx, b);
+  else
+    increments_one(jy, b - jx.n_paths);
+}
+
 // The same for d a multiple of 4 (then the padded row is the point row and
 // both are 16-byte aligned): four channels per thread with 16-byte loads and
 // stores, the same arithmetic per element.
@@ -116,20 +138,19 @@ __device__ __forceinline__ float increment_value(float a, float b, int32_t round
   return v * scale;
 }
 
-__global__ __launch_bounds__(256) void increments4_kernel(
-    const float* __restrict__ pts, const int64_t* __restrict__ off,
-    const int32_t* __restrict__ plan_n, const int64_t* __restrict__ plan_start, int32_t len,
-    int64_t n_paths, int32_t d, float scale, int32_t rounding, int32_t rep,
-    float* __restrict__ incr) {
-  const int64_t k = blockIdx.x;
-  if (k >= n_paths) return;
+__device__ __forceinline__ void increments4_one(const IncJob& j, int64_t k) {
+  const float* __restrict__ pts = j.pts;
+  const int64_t* __restrict__ off = j.off;
+  const int32_t len = j.len, d = j.d, rounding = j.rounding, rep = j.rep;
+  const float scale = j.scale;
+  float* __restrict__ incr = j.incr;
   int64_t pstart, dstart;
   int32_t n;
   if (off) {
-    n = plan_n[k];
+    n = j.plan_n[k];
     if (n <= 0) return;
     pstart = off[k];
-    dstart = plan_start[k] * rep;
+    dstart = j.plan_start[k] * rep;
   } else {
     n = len - 1;
     pstart = k * (int64_t)len;
@@ -159,6 +180,14 @@ __global__ __launch_bounds__(256) void increments4_kernel(
       ++row;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void increments4_kernel(const IncJob jx, const IncJob jy) {
+  const int64_t b = blockIdx.x;
+  if (b < jx.n_paths)
+    increments4_one(jx, b);
+  else
+    increments4_one(jy, b - jx.n_paths);
 }
 
 // Plans of a batch refined rep times: n -> n rep (broken paths keep n < 0),
@@ -245,21 +274,47 @@ hipError_t launch_plan(const Batch& b, PathPlan plan, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_increments(const Batch& b, const PathPlan* plan, float scale, int dpad,
-                             float* incr, hipStream_t stream, int rounding, int rep) {
-  if (b.n_paths == 0 || (!b.offsets && b.len < 2)) return hipSuccess;
-  if (b.dim % 4 == 0 && dpad == b.dim && reinterpret_cast<uintptr_t>(b.points) % 16 == 0 &&
-      reinterpret_cast<uintptr_t>(incr) % 16 == 0) {
-    hipLaunchKernelGGL(increments4_kernel, dim3((unsigned)b.n_paths), dim3(256), 0, stream,
-                       b.points, b.offsets, plan ? plan->n : nullptr,
-                       plan ? plan->start : nullptr, b.len, b.n_paths, b.dim,
-                       scale / (float)rep, rounding, rep, incr);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(increments_kernel, dim3((unsigned)b.n_paths), dim3(256), 0, stream,
-                     b.points, b.offsets, plan ? plan->n : nullptr,
-                     plan ? plan->start : nullptr, b.len, b.n_paths, b.dim, dpad,
-                     scale / (float)rep, rounding, rep, incr);
+namespace {
+IncJob make_job(const Batch& b, const PathPlan* plan, float scale, int dpad, float* incr,
+                int rounding, int rep) {
+  IncJob j{};
+  j.pts = b.points;
+  j.off = b.offsets;
+  j.plan_n = plan ? plan->n : nullptr;
+  j.plan_start = plan ? plan->start : nullptr;
+  j.len = b.len;
+  // a uniform batch of one-point paths has no increments
+  j.n_paths = (!b.offsets && b.len < 2) ? 0 : b.n_paths;
+  j.d = b.dim;
+  j.dpad = dpad;
+  j.scale = scale / (float)rep;
+  j.rounding = rounding;
+  j.rep = rep;
+  j.incr = incr;
+  return j;
+}
+
+// d a multiple of 4 with 16-byte aligned points and rows (or nothing to do)
+bool four_wide(const IncJob& j) {
+  return j.n_paths == 0 ||
+         (j.d % 4 == 0 && j.dpad == j.d && reinterpret_cast<uintptr_t>(j.pts) % 16 == 0 &&
+          reinterpret_cast<uintptr_t>(j.incr) % 16 == 0);
+}
+}  // namespace
+
+hipError_t launch_increments_xy(const Batch& bx, const PathPlan* planx, float scalex,
+                                const Batch& by, const PathPlan* plany, float scaley, int dpad,
+                                float* incx, float* incy, hipStream_t stream, int rounding,
+                                int rep) {
+  const IncJob jx = make_job(bx, planx, scalex, dpad, incx, rounding, rep);
+  const IncJob jy = make_job(by, plany, scaley, dpad, incy, rounding, rep);
+  const int64_t blocks = jx.n_paths + jy.n_paths;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  if (four_wide(jx) && four_wide(jy))
+    hipLaunchKernelGGL(increments4_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, jx, jy);
+  else
+    hipLaunchKernelGGL(increments_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, jx, jy);
   return hipGetLastError();
 }
 

@@ -36,19 +36,21 @@ hipError_t launch_plan(const Batch& b, PathPlan plan, hipStream_t stream);
 // replay it like any other launch)
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t stream);
 
-// Dense padded increments: row start[k] + p holds scale * (x_{p+1} - x_p),
-// p < n[k], zero-padded to `dpad` channels.  scale is a power of two.  With
-// rounding kRoundBf16 / kRoundF16 each increment is first rounded to that
-// 16-bit format (the inner products then see 16-bit inputs, float32 sums).
-// With rep > 1 (a power of two) every increment fills rep consecutive rows,
-// each scale * (x_{p+1} - x_p) / rep: the batch refined rep times, exactly
-// (rows start[k] rep + p rep + j).
+// Dense padded increments of both batches of a call, in one launch: row
+// start[k] + p of a batch's buffer holds scale * (x_{p+1} - x_p), p < n[k],
+// zero-padded to `dpad` channels (scalex for X, scaley for Y; powers of two).
+// With rounding kRoundBf16 / kRoundF16 each increment is first rounded to
+// that 16-bit format (the inner products then see 16-bit inputs, float32
+// sums).  With rep > 1 (a power of two) every increment fills rep
+// consecutive rows, each scale * (x_{p+1} - x_p) / rep: the batch refined rep
+// times, exactly (rows start[k] rep + p rep + j).
 enum { kRoundNone = 0, kRoundBf16 = 1, kRoundF16 = 2 };
-hipError_t launch_increments(const Batch& b, const PathPlan* plan, float scale, int dpad,
-                             float* incr, hipStream_t stream, int rounding = kRoundNone,
-                             int rep = 1);
+hipError_t launch_increments_xy(const Batch& bx, const PathPlan* planx, float scalex,
+                                const Batch& by, const PathPlan* plany, float scaley, int dpad,
+                                float* incx, float* incy, hipStream_t stream,
+                                int rounding = kRoundNone, int rep = 1);
 // The plan of a batch refined rep times: n[k] -> n[k] rep (for n[k] > 0),
-// start[k] -> start[k] rep.  Run after launch_increments has read the plan.
+// start[k] -> start[k] rep.  Run after the increments have read the plan.
 hipError_t launch_scale_plan(PathPlan plan, int64_t n_paths, int rep, hipStream_t stream);
 
 // Dense padded node rows (the points themselves): path k occupies rows
