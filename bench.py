@@ -762,6 +762,9 @@ def bench_pair(args):
     per_g, wall_g = time_steps(graph.replay, args.steps, args.warmup)
     us_e = wall_e * 1e6 / args.steps
     us_g = wall_g * 1e6 / args.steps
+    # the value is the faster of the two ways to call it (on this runtime a
+    # graph replay of its two small launches costs more than the eager call)
+    us_best, best_path = (us_g, "hipgraph_replay") if us_g <= us_e else (us_e, "eager_call")
     ref = float(oracle.pairs([x.astype(np.float64)], [y.astype(np.float64)], 0)[0])
     k = float(gout.item())
     # the straight segments: the scheme converges to k = sum_k <a,b>^k / (k!)^2
@@ -772,11 +775,12 @@ def bench_pair(args):
     seg = {f"order_{o}": sk.sigkernel_pair(xsd, ysd, o).item() for o in (0, 2, 4, 6, 8)}
     rec = {
         "metric": "pairs/s of single-pair calls (latency), 32-point pair in R^2, order 0",
-        "value": 1e6 / us_g, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": us_g / 1e3, "higher_is_better": True,
+        "value": 1e6 / us_best, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": us_best / 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "one pair, 32 points in R^2, N(0, 1/32) increments from 0, "
                                "dyadic order 0; and one straight-segment pair"},
+        "value_from": best_path,
         "us_per_pair": {"hipgraph_replay": us_g, "eager_call": us_e,
                         "gpu_event_per_launch": per_g[0] * 1e3},
         "rel_err_vs_oracle": abs(k - ref) / abs(ref),
