@@ -193,3 +193,26 @@ def test_matrix_core_row_stride():
     G = sk.sigkernel_increment_gram(Xc, Yc, ld=53, out=out).cpu().numpy()
     assert torch.all(out[..., 49:] == -7.0)
     assert np.array_equal(G, sk.sigkernel_increment_gram(Xc, Yc).cpu().numpy())
+
+
+@pytest.mark.parametrize("d", [5, 20])
+def test_pairs_mode_both_kernels(d):
+    # gram=False: pair k is (x_k, y_k), on the row kernel (d <= 16) and the
+    # matrix-core kernel (d > 16)
+    X = workloads.random_paths(950 + d, 3, 45, d)
+    Y = workloads.random_paths(960 + d, 3, 70, d)
+    G = sk.sigkernel_increment_gram(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(),
+                                    gram=False).cpu().numpy()
+    assert G.shape == (3, 44, 69)
+    ix, iy = rounded_increments(X, "f32"), rounded_increments(Y, "f32")
+    ref = np.einsum("kpc,kqc->kpq", ix, iy)
+    scale = np.einsum("kpc,kqc->kpq", np.abs(ix), np.abs(iy)).max()
+    assert np.abs(G - ref).max() <= d * 2.0 ** -23 * scale
+
+
+@pytest.mark.parametrize("d", [3, 30])
+def test_one_point_paths_give_an_empty_gram(d):
+    X = torch.from_numpy(workloads.random_paths(970, 2, 1, d)).cuda()
+    Y = torch.from_numpy(workloads.random_paths(971, 3, 40, d)).cuda()
+    G = sk.sigkernel_increment_gram(X, Y)
+    assert tuple(G.shape) == (2, 3, 0, 39)
