@@ -180,3 +180,28 @@ def test_autotune_refused_under_capture():
     assert lib.sigkernel_graph_end(s.cuda_stream, ctypes.byref(h)) == 0
     assert st == _lib.SK_ERR_STATE
     assert lib.sigkernel_graph_destroy(h) == 0
+
+
+@pytest.mark.parametrize("n", [33, 70, 129, 180, 260])
+def test_default_runs_symmetric_equals_full(n):
+    # the default run length follows a cost model of the busiest SIMD and so
+    # changes with n (here 1, 3, 3, 9 and 12 pairs per run for the upper
+    # triangle, more for the full square): the upper-triangle launch must give
+    # the full launch's values bit for bit, mirrored, and the unbiased form
+    # only a zero diagonal on top
+    X = cuda(workloads.random_paths(1100 + n, n, 24, 3))
+    full = sk.sigkernel_gram(X, X, 1)
+    sym = sk.sigkernel_gram(X, None, 1, symmetric=True)
+    iu = torch.triu_indices(n, n, device=X.device)
+    assert torch.equal(sym[iu[0], iu[1]], full[iu[0], iu[1]])
+    assert torch.equal(sym, sym.T)
+    nd = sk.sigkernel_gram(X, None, 1, symmetric=True, no_diag=True)
+    assert torch.all(torch.diagonal(nd) == 0)
+    off = ~torch.eye(n, dtype=torch.bool, device=X.device)
+    assert torch.equal(nd[off], sym[off])
+    # a sample of entries against the oracle
+    rng = np.random.default_rng(n)
+    idx = rng.choice(n * n, size=12, replace=False)
+    Xd = X.cpu().double().numpy()
+    ref = oracle.pairs([Xd[i // n] for i in idx], [Xd[i % n] for i in idx], 1)
+    assert mixed_err(sym.reshape(-1)[idx].cpu().numpy(), ref).max() <= TOL

@@ -148,3 +148,15 @@ def test_headline_shape_sampled():
     ref = oracle.lifted_rbf_pairs(xs, ys, 1, 0.5)
     assert mixed_err(K.reshape(-1)[idx], ref).max() <= TOL
     assert np.all(np.isfinite(K))
+
+
+@pytest.mark.parametrize("n", [70, 180])
+def test_symmetric_runs_equal_the_full_gram(n):
+    # default run lengths of the upper-triangle launch at sizes where they
+    # exceed one pair per run: bitwise the full launch's values
+    X = cuda(workloads.random_paths(1200 + n, n, 20, 3, std=1.0))
+    full = sk.sigkernel_gram_lifted(X, X, 1, sigma=0.6)
+    sym = sk.sigkernel_gram_lifted(X, None, 1, sigma=0.6, symmetric=True)
+    iu = torch.triu_indices(n, n, device=X.device)
+    assert torch.equal(sym[iu[0], iu[1]], full[iu[0], iu[1]])
+    assert torch.equal(sym, sym.T)
