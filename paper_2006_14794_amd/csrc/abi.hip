@@ -138,9 +138,11 @@ int64_t device_simds() {
 // (the wavefront fills once per run); the busiest SIMD holds
 // ceil(waves / SIMDs) waves, and a SIMD with one, two or three waves issues
 // at 0.73, 0.93 or 0.97 of its rate with four or more (measured on the
-// sweep).  A symmetric Gram counts only its upper triangle's runs.  At most
+// sweep).  A symmetric Gram counts only its upper triangle's runs (without
+// the diagonal when that is zeroed).  At most
 // 64 pairs per run; ties go to the shorter run.
-int64_t choose_sweep_run(int64_t nx, int64_t ny, int64_t cols, bool sym, int32_t tuned) {
+int64_t choose_sweep_run(int64_t nx, int64_t ny, int64_t cols, bool sym, int32_t tuned,
+                         bool no_diag = false) {
   if (tuned > 0 || ny <= 1 || cols <= 0) return choose_run(nx, ny, tuned);
   const int64_t simds = device_simds();
   const double fill = 64.0 / (double)cols;
@@ -149,7 +151,8 @@ int64_t choose_sweep_run(int64_t nx, int64_t ny, int64_t cols, bool sym, int32_t
   double best_cost = 0.0;
   for (int64_t run = 1; run <= cap; ++run) {
     const int64_t rpr = (ny + run - 1) / run;
-    const int64_t waves = sym ? sk::tri_runs(nx, rpr, run) : nx * rpr;
+    const int64_t s = sym && no_diag ? 1 : 0;
+    const int64_t waves = sym ? sk::tri_runs(nx - s, rpr, run, s) : nx * rpr;
     const int64_t per_simd = (waves + simds - 1) / simds;
     const double rate = per_simd >= 4 ? 1.0 : per_simd == 3 ? 0.97 : per_simd == 2 ? 0.93 : 0.73;
     const double cost = (double)per_simd * ((double)run + fill) / rate;
@@ -616,6 +619,21 @@ sk_status run_coef(const sk_paths* X, const sk_paths* Y, int32_t lam0, uint32_t 
   return SK_OK;
 }
 
+// A symmetric Gram's waves enumerate only the runs of its upper triangle; an
+// unbiased one (diagonal zeroed) leaves the diagonal out of them, and
+// zero_skipped_diagonal writes it.
+void set_triangle(sk::SweepArgs& a, int mode) {
+  if (mode != 2) return;
+  const int64_t s = a.no_diag ? 1 : 0;
+  a.tri = (int32_t)(1 + s);
+  a.n_waves = sk::tri_runs(a.nx - s, a.runs_per_row, a.run, s);
+}
+
+sk_status zero_skipped_diagonal(const sk::SweepArgs& a, hipStream_t stream) {
+  if (a.tri != 2 || !a.out) return SK_OK;
+  return sk::launch_zero_diag(a.out, a.nx, stream) == hipSuccess ? SK_OK : SK_ERR_HIP;
+}
+
 sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam0, uint32_t flags,
                       float* out, void* ws, size_t ws_bytes, hipStream_t stream, int mode) {
   if (X->dim > kMaxFusedDim)
@@ -691,17 +709,15 @@ sk_status run_forward(const sk_paths* X, const sk_paths* Y, int32_t lam0, uint32
     a.run = Y->offsets ? 1
                        : (int32_t)choose_sweep_run(X->n_paths, Y->n_paths,
                                                    (int64_t)(Y->len - 1) << lam, mode == 2,
-                                                   tune.run);
+                                                   tune.run, a.no_diag != 0);
     a.runs_per_row = (Y->n_paths + a.run - 1) / a.run;
     a.n_waves = X->n_paths * a.runs_per_row;
-    if (mode == 2) {  // only the runs of the upper triangle
-      a.tri = 1;
-      a.n_waves = sk::tri_runs(X->n_paths, a.runs_per_row, a.run);
-    }
+    set_triangle(a, mode);
   }
   const hipError_t e = sk::launch_sweep(a, lam, R, d, stream, tune.waves_per_block);
   if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;
-  return e == hipSuccess ? SK_OK : SK_ERR_HIP;
+  if (e != hipSuccess) return SK_ERR_HIP;
+  return zero_skipped_diagonal(a, stream);
 }
 
 // MMD^2 workspace: the three Gram blocks, the two upstream weight matrices,
@@ -930,17 +946,16 @@ sk_status run_lifted(const sk_paths* X, const sk_paths* Y, int32_t lam, uint32_t
   } else {
     a.run = Y->offsets ? 1
                        : (int32_t)choose_sweep_run(X->n_paths, Y->n_paths,
-                                                   (int64_t)(Y->len - 1) << lam, mode == 2, 0);
+                                                   (int64_t)(Y->len - 1) << lam, mode == 2, 0,
+                                                   a.no_diag != 0);
     a.runs_per_row = (Y->n_paths + a.run - 1) / a.run;
     a.n_waves = X->n_paths * a.runs_per_row;
-    if (mode == 2) {  // only the runs of the upper triangle
-      a.tri = 1;
-      a.n_waves = sk::tri_runs(X->n_paths, a.runs_per_row, a.run);
-    }
+    set_triangle(a, mode);
   }
   const hipError_t e = sk::launch_lifted(a, lam, R, d, stream, 0);
   if (e == hipErrorInvalidValue) return SK_ERR_UNSUPPORTED;
-  return e == hipSuccess ? SK_OK : SK_ERR_HIP;
+  if (e != hipSuccess) return SK_ERR_HIP;
+  return zero_skipped_diagonal(a, stream);
 }
 
 }  // namespace

@@ -26,7 +26,8 @@ struct SweepArgs {
   double lift_scale;        // lifted sweep: 2^-(2 lam + 1), the coefficient's fine-cell factor
   int32_t run;              // pairs streamed through one wave (Gram with uniform y)
   int64_t runs_per_row;     // ceil(ny / run)
-  int32_t tri;              // mode 2: waves enumerate only the runs that hold pairs (tri_runs)
+  int32_t tri;       // mode 2: waves enumerate only the runs of the upper triangle
+                     // (tri_runs): 1 with the diagonal, 2 without it
   int64_t n_waves;
   float* out;               // nullptr: terminal values not written
   int64_t out_ld;           // ny for the Gram
@@ -50,14 +51,17 @@ __host__ __device__ inline int64_t sweep_steps(int64_t total) {
   return ((total + 63 + 2) / 3) * 3;
 }
 
-// The upper triangle of a symmetric Gram by runs: row i (x_i) has runs of
-// y columns starting at multiples of `run`, the one holding column i
-// clipped to start there, so it holds runs_per_row - floor(i / run) runs.
-// Waves enumerated over these alone (no wave without a pair) are spread
-// evenly over the compute units; tri_runs(i) counts the runs of rows
-// 0 .. i-1.
-__host__ __device__ inline int64_t tri_runs(int64_t i, int64_t runs_per_row, int64_t run) {
-  const int64_t q = i / run, r = i - q * run;
+// The upper triangle of a symmetric Gram by runs: row i (x_i) takes the y
+// columns from i + s on (s = 0 with the diagonal, 1 without it) in runs that
+// start at multiples of `run`, the one holding column i + s clipped to start
+// there, so it holds runs_per_row - floor((i + s) / run) runs (rows
+// i < nx - s; without the diagonal the last row has none).  Waves enumerated
+// over these alone (no wave without a pair) are spread evenly over the
+// compute units; tri_runs(i) counts the runs of rows 0 .. i-1:
+//   i runs_per_row - sum_{j < i + s} floor(j / run).
+__host__ __device__ inline int64_t tri_runs(int64_t i, int64_t runs_per_row, int64_t run,
+                                            int64_t s = 0) {
+  const int64_t x = i + s, q = x / run, r = x - q * run;
   return i * runs_per_row - (run * q * (q - 1) / 2 + q * r);
 }
 

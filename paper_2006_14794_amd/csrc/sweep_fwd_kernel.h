@@ -149,16 +149,20 @@ __device__ __forceinline__ bool wave_run(const SweepArgs& a, int64_t w, int lane
     b0 = w;
     b1 = w + 1;
   } else if (a.tri) {
+    // s = 1: the triangle without its diagonal (the host zeroes it)
+    const int64_t s = a.tri - 1;
     // the last row whose runs start at or before wave w (binary search on
     // the increasing run counts; the values are uniform over the wave)
-    int64_t lo = 0, hi = a.nx;
+    int64_t lo = 0, hi = a.nx - s;
     while (hi - lo > 1) {
       const int64_t mid = (lo + hi) >> 1;
-      if (tri_runs(mid, a.runs_per_row, a.run) <= w) lo = mid; else hi = mid;
+      if (tri_runs(mid, a.runs_per_row, a.run, s) <= w) lo = mid; else hi = mid;
     }
     ia = lo;
-    b0 = (ia / a.run + (w - tri_runs(ia, a.runs_per_row, a.run))) * a.run;
-    b1 = b0 + a.run < a.ny ? b0 + a.run : a.ny;
+    const int64_t start =
+        ((ia + s) / a.run + (w - tri_runs(ia, a.runs_per_row, a.run, s))) * a.run;
+    b0 = start > ia + s ? start : ia + s;  // the row's first run begins at column ia + s
+    b1 = start + a.run < a.ny ? start + a.run : a.ny;
   } else {
     ia = w / a.runs_per_row;
     b0 = (w - ia * a.runs_per_row) * a.run;
