@@ -642,6 +642,26 @@ def bench_increment_gram(args):
            "roofline": {"bound": "hbm", "achieved": head["hbm_GBps"], "peak": 8000.0,
                         "unit": "GB/s", "frac": head["frac_of_8TBps"], "traffic": None},
            "layouts": recs}
+    if not args.no_cpu_baseline:
+        import oracle
+        # a sample of the pairs through the oracle's FP64 Gram on one host
+        # thread, its entries counted at the 4 bytes the GPU writes; the
+        # sample's entries are also compared with the GPU's dense float32 ones
+        rng = np.random.default_rng(0)
+        pick = rng.choice(nx * Y.shape[0], size=2048, replace=False)
+        Xd, Yd = X.astype(np.float64), Y.astype(np.float64)
+        t0 = time.perf_counter()
+        refs = [oracle.increment_gram(Xd[k // Y.shape[0]], Yd[k % Y.shape[0]]) for k in pick]
+        dt = time.perf_counter() - t0
+        sk.sigkernel_increment_gram(Xt, Yt, out=outs["dense"])  # float32 inputs
+        dense = outs["dense"].reshape(-1, n, n)
+        err = max(float(np.abs(dense[int(k)].cpu().numpy() - r).max()) for k, r in
+                  zip(pick[:64], refs[:64]))
+        rec["cpu_baseline"] = {"value": len(pick) * n * n * 4 / dt / 1e9, "unit": "GB/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{len(pick)} of the {nx * Y.shape[0]} pairs on one host "
+                                         f"thread, {dt:.2f} s", **host_cpu()}
+        rec["max_abs_err_vs_oracle_on_64_pairs"] = err
     emit(rec)
 
 
