@@ -626,7 +626,7 @@ void set_triangle(sk::SweepArgs& a, int mode) {
   if (mode != 2) return;
   const int64_t s = a.no_diag ? 1 : 0;
   a.tri = (int32_t)(1 + s);
-  a.n_waves = sk::tri_runs(a.nx - s, a.runs_per_row, a.run, s);
+  a.n_waves = a.nx > s ? sk::tri_runs(a.nx - s, a.runs_per_row, a.run, s) : 0;
 }
 
 sk_status zero_skipped_diagonal(const sk::SweepArgs& a, hipStream_t stream) {
