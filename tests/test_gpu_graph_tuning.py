@@ -205,3 +205,30 @@ def test_default_runs_symmetric_equals_full(n):
     Xd = X.cpu().double().numpy()
     ref = oracle.pairs([Xd[i // n] for i in idx], [Xd[i % n] for i in idx], 1)
     assert mixed_err(sym.reshape(-1)[idx].cpu().numpy(), ref).max() <= TOL
+
+
+@pytest.mark.parametrize("scheme", ["explicit", "implicit"])
+def test_unbiased_symmetric_without_diagonal_sweeps(scheme):
+    # the unbiased Gram's triangle leaves the diagonal out of its waves and
+    # zeroes it separately: the off-diagonal values are the full launch's,
+    # bit for bit, for uniform and ragged batches and both schemes
+    n = 41
+    X = cuda(workloads.random_paths(1300, n, 30, 4))
+    full = sk.sigkernel_gram(X, X, 1, scheme=scheme)
+    nd = sk.sigkernel_gram(X, None, 1, symmetric=True, no_diag=True, scheme=scheme)
+    off = ~torch.eye(n, dtype=torch.bool, device=X.device)
+    assert torch.equal(nd[off], full[off])
+    assert torch.all(torch.diagonal(nd) == 0)
+    lens = [1, 2, 17, 30, 9, 2, 25]
+    xs = [workloads.random_paths(1310 + i, 1, L, 3)[0] for i, L in enumerate(lens)]
+    R = RaggedPaths.from_list(xs, "cuda")
+    fullr = sk.sigkernel_gram(R, R, 2, scheme=scheme)
+    ndr = sk.sigkernel_gram(R, None, 2, symmetric=True, no_diag=True, scheme=scheme)
+    offr = ~torch.eye(len(lens), dtype=torch.bool, device=X.device)
+    assert torch.equal(ndr[offr], fullr[offr])
+    assert torch.all(torch.diagonal(ndr) == 0)
+    lifted_full = sk.sigkernel_gram_lifted(X, X, 1, sigma=0.7, scheme=scheme)
+    lifted_nd = sk.sigkernel_gram_lifted(X, None, 1, sigma=0.7, symmetric=True, no_diag=True,
+                                         scheme=scheme)
+    assert torch.equal(lifted_nd[off], lifted_full[off])
+    assert torch.all(torch.diagonal(lifted_nd) == 0)
